@@ -1,0 +1,165 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the acoustic forward operator on one MI355X.
+
+Workload: 3-D acoustic forward, 256^3 physical grid + 40-point absorbing
+layer on every side (336^3 computed points), h = 10 m, space order 8,
+1000 time samples (999 steps), seeded layered model (6-10 layers, 1.5-4.5
+km/s increasing with depth, 2% Gaussian noise), 15 Hz Ricker at an off-grid
+point near the surface, 256 x 256 receivers at 25 m depth, FP32.
+
+One benchmark "step" is one full shot: 999 stencil updates, each followed by
+the source injection and the sampling of all 65 536 receivers, with inputs
+resident in HBM.  value = computed grid-point updates per second
+(336^3 * 999 per step).
+
+Also reported: the stencil kernel's average launch duration (HIP events
+around a stencil-only pass on the same stream) against the 8 TB/s HBM roofline
+at 16 algorithmic bytes per point update, and the FP64 CPU oracle timed on a
+few steps of the same grid.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_UPDATE = 16.0     # read u[n], u[n-1], C; write u[n+1]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(shot, dt, steps):
+    """The FP64 oracle, untuned, on `steps` time steps of the same grid."""
+    import oracle
+    prob = oracle.Problem(shot.shape, shot.spacing, shot.order, shot.nbl, dt, steps + 1, shot.src_coords,
+                          shot.rec_coords, damp_power=shot.damp_power, damp_R=shot.damp_R,
+                          damp_vref=shot.damp_vref)
+    op = oracle.Operator(prob, shot.m)
+    w = shot.wavelet(dt)[: steps + 1]
+    t0 = time.perf_counter()
+    op.forward(w)
+    t = time.perf_counter() - t0
+    npad = int(np.prod(prob.padded_shape))
+    return {"value": npad * steps / t, "unit": "grid-pt updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} steps (with injection and receiver sampling) of the same "
+                      f"{'x'.join(map(str, prob.padded_shape))} grid, NumPy FP64, single-threaded",
+            "seconds": round(t, 3)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cpu-steps", type=int, default=4, help="oracle time steps for the CPU baseline (0 = skip)")
+    ap.add_argument("--n", type=int, default=256, help="physical grid points per axis")
+    ap.add_argument("--nt", type=int, default=1000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (shots would shard one per GPU, "
+              "see DESIGN.md); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1608_08658_amd as awe
+    import synth
+
+    torch.cuda.set_device(0)
+    shot = synth.config_3d_forward(n=args.n, nt=args.nt)
+    dt = shot.dt_factor * awe.dt_max(3, shot.order, shot.spacing, shot.vmax)
+    log(f"workload {shot.name}: padded {[n + 2 * shot.nbl for n in shot.shape]}, dt {dt:.4e} s")
+    plan = awe.Plan(shape=shot.shape, spacing=shot.spacing, space_order=shot.order, nbl=shot.nbl, dt=dt,
+                    nt=shot.nt, src_coords=shot.src_coords, rec_coords=shot.rec_coords,
+                    damp_power=shot.damp_power, damp_R=shot.damp_R, damp_vref=shot.damp_vref)
+    npad = int(np.prod(plan.padded))
+    m = torch.tensor(shot.m, dtype=torch.float32, device="cuda")
+    w = torch.tensor(shot.wavelet(dt), dtype=torch.float32, device="cuda")
+    traces = torch.empty((shot.nt, len(shot.rec_coords)), dtype=torch.float32, device="cuda")
+    t0 = time.perf_counter()
+    plan.set_model(m)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+
+    for i in range(args.warmup):
+        plan.forward(w, traces=traces)
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{args.warmup} done")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    for i in range(args.steps):
+        plan.forward(w, traces=traces)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    ms_per_step = gpu_ms / args.steps
+    updates = npad * (shot.nt - 1)
+    value = updates * args.steps / (gpu_ms / 1e3)
+    finite = bool(torch.isfinite(traces).all().item())
+    log(f"timed {args.steps} shots: {gpu_ms:.1f} ms GPU ({wall:.2f} s wall), {value / 1e9:.1f} Gpt/s, finite={finite}")
+
+    # stencil-only pass on the same stream: average duration of one stencil launch
+    nk = shot.nt - 1
+    k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    k0.record()
+    plan.step(0, nk)
+    k1.record()
+    torch.cuda.synchronize()
+    kern_s = k0.elapsed_time(k1) / 1e3 / nk
+    achieved = BYTES_PER_UPDATE * npad / kern_s / 1e9
+    log(f"stencil kernel: {kern_s * 1e6:.1f} us/launch, {achieved:.0f} GB/s algorithmic "
+        f"({100 * achieved / HBM_PEAK_GBS:.1f}% of {HBM_PEAK_GBS:.0f} GB/s)")
+    plan.close()
+
+    base = None
+    if args.cpu_steps > 0:
+        log(f"CPU oracle baseline: {args.cpu_steps} steps ...")
+        base = cpu_baseline(shot, dt, args.cpu_steps)
+        log(f"  {base['value'] / 1e6:.2f} Mpt/s in {base['seconds']} s")
+
+    out = {
+        "metric": "grid-pt updates/s",
+        "value": value,
+        "unit": "grid-pt updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"3-D acoustic forward shot, {args.n}^3 physical + 40-point layer "
+                        f"({'x'.join(map(str, plan.padded))} computed), order 8, {shot.nt} samples, "
+                        f"layered model, 15 Hz Ricker, {len(shot.rec_coords)} receivers",
+            "grid": list(plan.padded), "space_order": shot.order, "nt": shot.nt,
+            "nrec": len(shot.rec_coords), "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "step3d<M=4> (forward stencil)", "avg_launch_us": kern_s * 1e6,
+            "bytes_per_update": BYTES_PER_UPDATE, "updates_per_launch": npad,
+        },
+        "cpu_baseline": base,
+        "setup_s": round(setup_s, 3),
+        "traces_finite": finite,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

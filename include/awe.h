@@ -1,0 +1,228 @@
+/*
+ * awe.h - C ABI of an acoustic wave-equation engine for AMD MI355X (gfx950).
+ *
+ * The operator is the explicit finite-difference scheme for
+ *
+ *     m u_tt + eta u_t - laplace(u) = q,      u = u_t = 0 at t = 0,
+ *
+ * i.e. Eq. (1) of Kukreja et al., "Devito: automated fast finite difference
+ * computation" (arXiv:1608.08658, Sec. V.A) with the damping term of its
+ * Listing 1: second order in time, even order P = 2..16 in space, an
+ * absorbing layer of nbl points on every side of the physical model, source
+ * injection and receiver interpolation at off-grid points (Sec. IV).  The
+ * adjoint run backwards in time (Eq. 4, Listing 2) and the adjoint-state
+ * gradient of the L2 trace misfit (Eqs. 2-3) are provided with periodic
+ * wavefield checkpointing and recomputation.
+ *
+ * Conventions for every call
+ *   - Layout: arrays are FP32, C order, axis 0 = depth (slowest), the last
+ *     axis unit stride.  "physical" arrays have the model's shape; "padded"
+ *     arrays have shape[a] + 2 nbl points on every axis.
+ *   - Units: SI.  m is squared slowness (s^2/m^2), spacing in metres, dt in
+ *     seconds, coordinates in metres from the first physical grid point.
+ *   - Pointers named *_dev are device pointers on the plan's device; *_host
+ *     are host pointers.  The caller owns every pointer it passes; the library
+ *     never frees or keeps a caller pointer beyond the call, except where a
+ *     call says so (the server keeps traces_host until the request is done).
+ *   - Streams: awe_stream is a hipStream_t (NULL = the legacy default stream).
+ *     Calls enqueue work on that stream and return without waiting for it,
+ *     except where a call says it synchronises.  The caller synchronises the
+ *     stream before reading results.
+ *   - Errors: every call returns an awe_status; AWE_OK is 0 and errors are
+ *     negative.  Nothing aborts.  awe_last_error() gives a message for the
+ *     last failing call on the calling thread.  Arguments are validated
+ *     before any work is enqueued.
+ *   - Threading: a plan is not re-entrant; different plans may be used from
+ *     different threads on different streams.
+ */
+#ifndef AWE_H
+#define AWE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t awe_status;
+
+enum {
+    AWE_OK = 0,
+    AWE_EINVAL = -1,     /* invalid argument or geometry                         */
+    AWE_ENOMEM = -2,     /* device allocation failed or budget exceeded           */
+    AWE_EHIP = -3,       /* a HIP runtime call failed (message has HIP's text)    */
+    AWE_ESTATE = -4,     /* call out of order (e.g. gradient before forward)      */
+    AWE_EUNSTABLE = -5,  /* dt above the stability limit, or non-finite values    */
+    AWE_EBUSY = -6,      /* server queue full or request still running            */
+    AWE_ENODEV = -7      /* no usable gfx950 device                               */
+};
+
+typedef void* awe_stream;
+typedef struct awe_plan_s* awe_plan;
+typedef struct awe_server_s* awe_server;
+
+/*
+ * One modelling problem (everything except the model and the wavelet).
+ * Sec. V.C passes model, nt, dt, h and the space order to forward() and
+ * adjoint() (Listings 1-2); the generated operator also takes source and
+ * receiver coordinates (Listing 3).
+ */
+typedef struct awe_geometry {
+    int32_t ndim;            /* 2 or 3                                               */
+    int32_t space_order;     /* even, 2..16                                          */
+    int64_t shape[3];        /* physical points per axis (first ndim used), >= 2     */
+    double spacing[3];       /* metres per axis (first ndim used), > 0               */
+    int32_t nbl;             /* absorbing points added on every side, >= 0           */
+    int32_t damp_power;      /* k of the layer profile eta_max (d/nbl)^k, 1..4       */
+    double damp_R;           /* target round-trip reflection, 0 < R < 1              */
+    double damp_vref;        /* reference speed in eta_max (m/s), > 0                */
+    double dt;               /* time step (s), > 0, <= awe_dt_max of the model      */
+    int32_t nt;              /* time samples; nt-1 steps are taken, >= 1             */
+    int32_t nsrc;            /* >= 0                                                 */
+    int32_t nrec;            /* >= 0                                                 */
+    int32_t reserved;        /* must be 0                                            */
+    const double* src_coords;  /* host [nsrc][ndim]; copied by awe_plan_create       */
+    const double* rec_coords;  /* host [nrec][ndim]; copied by awe_plan_create       */
+} awe_geometry;
+
+/* Text for the last error on the calling thread ("" if none).  The string
+ * stays valid until the next failing call on the same thread. */
+const char* awe_last_error(void);
+
+/* Library version string, e.g. "awe 0.1 gfx950". */
+const char* awe_version(void);
+
+/*
+ * Weights c_0..c_M (M = order/2) of the central second derivative of even
+ * order `order` on a unit grid (Sec. IV.A.1; for order 2 they are -2, 1).
+ * w_host must hold M+1 doubles.  Pure host function.
+ */
+awe_status awe_fd_weights(int32_t order, double* w_host);
+
+/*
+ * Stability limit of the undamped scheme for speeds <= vmax:
+ * dt_max = 2 / (vmax sqrt(sum_a sum_{k=-M..M} |c_k| / h_a^2)).
+ * spacing_host holds ndim values.  Pure host function.
+ */
+awe_status awe_dt_max(int32_t ndim, int32_t order, const double* spacing_host, double vmax, double* dt_max);
+
+/*
+ * Device bytes a plan for `g` holds: forward only (ckpt_every == 0) or
+ * forward + gradient with checkpoints every ckpt_every steps.  Used for
+ * admission control.  Pure host function.
+ */
+awe_status awe_footprint(const awe_geometry* g, int32_t ckpt_every, uint64_t* bytes);
+
+/*
+ * Validate `g`, build the off-grid point tables and allocate the plan's
+ * forward fields on the current HIP device.  Coordinates outside the padded
+ * grid are AWE_EINVAL.  The plan owns every device buffer it allocates;
+ * awe_plan_destroy frees them.  Synchronous.
+ */
+awe_status awe_plan_create(const awe_geometry* g, awe_plan* out);
+awe_status awe_plan_destroy(awe_plan plan);
+
+/* Padded grid of a plan: out_host[0..2] = padded points per axis (1 beyond
+ * ndim), out_host[3] = device bytes currently held. */
+awe_status awe_plan_info(awe_plan plan, int64_t* out_host);
+
+/*
+ * Load the physical model m_dev (physical shape, squared slowness) and build
+ * the update coefficients on the padded grid (the layer copies the nearest
+ * edge cell of the model).  Checks that m is finite and positive and that
+ * dt <= awe_dt_max(max speed): otherwise AWE_EUNSTABLE.  Synchronises
+ * `stream` (it reads the model's extrema back to the host).
+ */
+awe_status awe_set_model(awe_plan plan, const float* m_dev, awe_stream stream);
+
+/*
+ * Forward modelling (Eq. 1, Listing 1) from zero initial state:
+ *   u[n+1] = (2-a) u[n] - (1-a) u[n-1] + C (L u[n] + S q[n]),  n = 0..nt-2,
+ *   traces[n] = R u[n]  (traces[0] = 0),
+ * with C = dt^2 / (m + eta dt/2), a = eta C / dt.
+ * wavelet_dev: [nt][nsrc] source signatures at t = n dt (may be NULL when
+ * nsrc == 0).  traces_dev: [nt][nrec] output (may be NULL when nrec == 0).
+ * ckpt_every > 0 stores the state pair every ckpt_every steps (and a copy of
+ * the wavelet) for a following awe_adjoint with a gradient; 0 stores
+ * nothing.  The final state stays in the plan (awe_get_state).
+ */
+awe_status awe_forward(awe_plan plan, const float* wavelet_dev, float* traces_dev,
+                       int32_t ckpt_every, awe_stream stream);
+
+/*
+ * Adjoint modelling (Eq. 4, Listing 2) driven by receiver data resid_dev
+ * [nt][nrec], run backwards in time:
+ *   mu[n] = (2-a) mu[n+1] - (1-a) mu[n+2] + C (L mu[n+1] + R^T y[n]),
+ * src_adj_dev (optional, [nt][nsrc]) receives F^T y: S^T mu[n+1] for
+ * n <= nt-2 and 0 for n = nt-1, so that <F x, y> = <x, F^T y> (Eqs. 5-6).
+ * grad_m_dev (optional, physical shape) receives the gradient of
+ * 1/2 ||traces - d_obs||^2 with respect to the physical m when resid_dev =
+ * traces - d_obs (Eq. 3, the exact derivative of the discrete misfit);
+ * it needs the preceding awe_forward on this plan to have used
+ * ckpt_every > 0 (else AWE_ESTATE).  Segments are recomputed from the
+ * checkpoints during the sweep.
+ */
+awe_status awe_adjoint(awe_plan plan, const float* resid_dev, float* src_adj_dev,
+                       float* grad_m_dev, awe_stream stream);
+
+/* The padded gradient of the last awe_adjoint that produced one
+ * (padded shape, dense).  AWE_ESTATE if there is none. */
+awe_status awe_get_gradient_padded(awe_plan plan, float* g_pad_dev, awe_stream stream);
+
+/*
+ * State access for restarts and tests: the state is the pair
+ * (u[n], u[n-1]) as dense padded arrays.  awe_set_state copies them in;
+ * awe_step then advances `nsteps` steps from time index n0, injecting
+ * wavelet rows n0..n0+nsteps-1 (wavelet_dev [nt][nsrc], may be NULL) and
+ * writing traces rows n0+1..n0+nsteps (traces_dev [nt][nrec], may be NULL);
+ * n0 + nsteps must be <= nt - 1.  awe_get_state copies the current pair out.
+ */
+awe_status awe_set_state(awe_plan plan, const float* u_dev, const float* u_prev_dev, awe_stream stream);
+awe_status awe_step(awe_plan plan, int32_t n0, int32_t nsteps, const float* wavelet_dev,
+                    float* traces_dev, awe_stream stream);
+awe_status awe_get_state(awe_plan plan, float* u_dev, float* u_prev_dev, awe_stream stream);
+
+/*
+ * Misfit of Eq. (2): resid_dev = traces_dev - d_obs_dev (n values) and
+ * *phi_host = 1/2 sum resid^2 accumulated in FP64 in a fixed order
+ * (deterministic).  resid_dev may be NULL.  Synchronises `stream`.
+ */
+awe_status awe_misfit(const float* traces_dev, const float* d_obs_dev, int64_t n,
+                      float* resid_dev, double* phi_host, awe_stream stream);
+
+/* ---------------------------------------------------------------------------
+ * Serving: a shot server with continuous batching on the current device.
+ * Requests carry their own geometry, model and wavelet (host memory, copied
+ * at submit).  An engine thread admits queued requests while the sum of
+ * their awe_footprint stays within hbm_fraction of the device memory that
+ * was free at creation and at most max_active run at once; every iteration
+ * advances every running request by up to chunk_steps time steps, and a
+ * request that finishes is retired and its traces copied to traces_host
+ * (host [nt][nrec], kept by the server until the request is done).
+ * ------------------------------------------------------------------------- */
+enum { AWE_REQ_QUEUED = 0, AWE_REQ_RUNNING = 1, AWE_REQ_DONE = 2, AWE_REQ_FAILED = 3 };
+
+awe_status awe_server_create(double hbm_fraction, int32_t chunk_steps, int32_t max_active,
+                             awe_server* out);
+/* Copies g (and its coordinates), m_host (physical shape) and wavelet_host
+ * ([nt][nsrc]).  Returns a ticket >= 0.  Non-blocking. */
+awe_status awe_server_submit(awe_server srv, const awe_geometry* g, const float* m_host,
+                             const float* wavelet_host, float* traces_host, int64_t* ticket);
+/* state = AWE_REQ_*; times_host[4] = (submit, admit, start, done) in seconds
+ * on the server's monotonic clock (-1 where not reached yet).  For a failed
+ * request *state is AWE_REQ_FAILED and awe_last_error() holds its message. */
+awe_status awe_server_poll(awe_server srv, int64_t ticket, int32_t* state, double* times_host);
+/* Blocks until the request is done or failed, or timeout_s elapses (AWE_EBUSY). */
+awe_status awe_server_wait(awe_server srv, int64_t ticket, double timeout_s);
+/* out_host[0..7] = (submitted, admitted, completed, failed, running, queued,
+ * bytes reserved, iterations). */
+awe_status awe_server_stats(awe_server srv, int64_t* out_host);
+/* Waits for running requests, drops queued ones (marked failed), frees all. */
+awe_status awe_server_destroy(awe_server srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AWE_H */

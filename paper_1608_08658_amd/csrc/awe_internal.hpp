@@ -1,0 +1,80 @@
+// Internal declarations shared by the host engine and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace awe {
+
+constexpr int kMaxHalf = 8;      // M = P/2 for space order P <= 16
+constexpr int kXOff = 32;        // interior x offset in floats (128-byte aligned rows)
+constexpr int kTileX = 64;       // one wavefront spans 64 unit-stride points
+
+// Device layout of every wavefield-sized array.  The padded computational grid
+// (physical model + absorbing layer) of extents n[0] x n[1] x n[2] (z, y, x;
+// n[1] = 1 in 2-D) sits inside a larger pitched allocation whose extra cells
+// are zero and never written: M planes above and below, M rows on each side
+// (3-D only) and kXOff / >= M columns on the left / right.  The stencil thus
+// reads its zero boundary from memory instead of branching, and every row of
+// the grid starts on a 128-byte boundary.
+struct Layout {
+    int ndim = 0;
+    int half = 0;                // M
+    int64_t n[3] = {1, 1, 1};    // computational extents (z, y, x)
+    int64_t sy = 0, sz = 0;      // strides in elements (x stride is 1)
+    int64_t origin = 0;          // element offset of grid point (0, 0, 0)
+    int64_t total = 0;           // elements in the allocation
+    int64_t points() const { return n[0] * n[1] * n[2]; }
+    int64_t index(int64_t z, int64_t y, int64_t x) const { return origin + z * sz + y * sy + x; }
+};
+
+// FD weights pre-scaled by 1 / h_a^2, and the time-step constant.
+struct StencilCoef {
+    float cz[kMaxHalf + 1];
+    float cy[kMaxHalf + 1];
+    float cx[kMaxHalf + 1];
+    float c0;                    // c_0 * sum_a 1 / h_a^2
+    float inv_dt;
+};
+
+// Arguments of one stencil step.  out may alias up (in-place update): every
+// thread reads up at a point before it writes out at the same point, and no
+// other thread touches that point.
+struct StepArgs {
+    const float* uc;             // u[n] (forward) / mu[n+1] (adjoint): stencil input
+    const float* up;             // u[n-1] / mu[n+2]
+    float* out;                  // u[n+1] / mu[n]
+    const float* coef;           // C = dt^2 / (m + eta dt / 2)
+    const float* eta_z;          // per-axis damping tables (eta = sum of the three)
+    const float* eta_y;
+    const float* eta_x;
+    const float* usnap;          // imaging only: forward wavefield u[n]
+    float* grad;                 // imaging only: accumulates u[n] * (mu[n] - 2 mu[n+1] + mu[n+2])
+};
+
+// Kernel launchers (kernels_stencil.hip, kernels_aux.hip).  All return the
+// launch status; none synchronise.
+hipError_t launch_step(const Layout& L, const StencilCoef& k, const StepArgs& a, bool imaging,
+                       int tile_cfg, int zchunk, hipStream_t s);
+int num_tile_cfgs(int ndim);
+int tile_rows(int ndim, int tile_cfg);   // y rows (3-D) or z chunks per block (2-D)
+
+hipError_t launch_inject(float* field, const float* coef, const int64_t* node, const int32_t* rowptr,
+                         const int32_t* pt, const float* w, int32_t nrows, const float* values, float scale,
+                         const float* usnap, float* grad, hipStream_t s);
+hipError_t launch_sample(float* out, const float* field, const int64_t* node, const float* w, int32_t npts,
+                         int32_t corners, float scale, hipStream_t s);
+hipError_t launch_coef(float* coef, const float* m_phys, const Layout& L, const int64_t phys[3], int nbl,
+                       const double* eta_z, const double* eta_y, const double* eta_x, double dt, hipStream_t s);
+hipError_t launch_minmax(const float* m, int64_t n, float* partial /* [3 * blocks] */, int blocks, hipStream_t s);
+hipError_t launch_fold(float* grad_phys, const float* g, const Layout& L, const int64_t phys[3], int nbl,
+                       float scale, hipStream_t s);
+hipError_t launch_pack(float* dense, const float* pitched, const Layout& L, float scale, hipStream_t s);
+hipError_t launch_unpack(float* pitched, const float* dense, const Layout& L, hipStream_t s);
+hipError_t launch_misfit(const float* tr, const float* obs, int64_t n, float* resid, double* partial,
+                         int blocks, double* result, hipStream_t s);
+hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);
+constexpr int kReduceBlocks = 1024;
+
+}  // namespace awe

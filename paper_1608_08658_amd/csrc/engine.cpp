@@ -1,0 +1,571 @@
+// Host engine behind the C ABI of include/awe.h: validation, FD weights,
+// stability limit, damping and off-grid tables, plans, and the forward /
+// adjoint / gradient drivers with periodic checkpointing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "awe.h"
+#include "awe_internal.hpp"
+#include "engine.hpp"
+
+namespace awe {
+
+thread_local std::string t_err;
+
+awe_status fail(awe_status code, const char* fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    t_err = buf;
+    return code;
+}
+
+#define AWE_HIP(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess) return fail(AWE_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// FD weights (Sec. IV.A.1): central second derivative of order P = 2M,
+//   c_k = 2 (-1)^(k+1) (M!)^2 / (k^2 (M-k)! (M+k)!),  c_0 = -2 sum_k c_k
+// (closed form of Fornberg, Math. Comp. 1988).  For M <= 8 numerator and
+// denominator are integers below 2^53, so each c_k is one correctly rounded
+// division.
+// ---------------------------------------------------------------------------
+void fd_weights(int order, double* w) {
+    const int m = order / 2;
+    auto fact = [](int n) { double f = 1.0; for (int i = 2; i <= n; ++i) f *= i; return f; };
+    double sum = 0.0;
+    for (int k = 1; k <= m; ++k) {
+        const double num = 2.0 * fact(m) * fact(m);
+        const double den = double(k) * double(k) * fact(m - k) * fact(m + k);
+        w[k] = ((k % 2) ? 1.0 : -1.0) * (num / den);
+        sum += w[k];
+    }
+    w[0] = -2.0 * sum;
+}
+
+double dt_limit(int ndim, int order, const double* h, double vmax) {
+    double c[kMaxHalf + 1];
+    fd_weights(order, c);
+    double s = std::fabs(c[0]);
+    for (int k = 1; k <= order / 2; ++k) s += 2.0 * std::fabs(c[k]);
+    double acc = 0.0;
+    for (int a = 0; a < ndim; ++a) acc += s / (h[a] * h[a]);
+    return 2.0 / (vmax * std::sqrt(acc));
+}
+
+awe_status validate(const awe_geometry* g) {
+    if (!g) return fail(AWE_EINVAL, "geometry is NULL");
+    if (g->ndim != 2 && g->ndim != 3) return fail(AWE_EINVAL, "ndim must be 2 or 3 (got %d)", g->ndim);
+    if (g->space_order < 2 || g->space_order > 2 * kMaxHalf || g->space_order % 2)
+        return fail(AWE_EINVAL, "space_order must be even in 2..16 (got %d)", g->space_order);
+    if (g->nbl < 0 || g->nbl > 4096) return fail(AWE_EINVAL, "nbl must be in 0..4096 (got %d)", g->nbl);
+    for (int a = 0; a < g->ndim; ++a) {
+        if (g->shape[a] < 2 || g->shape[a] + 2 * (int64_t)g->nbl > (1 << 20))
+            return fail(AWE_EINVAL, "shape[%d] = %lld out of range", a, (long long)g->shape[a]);
+        if (!(g->spacing[a] > 0.0) || !std::isfinite(g->spacing[a]))
+            return fail(AWE_EINVAL, "spacing[%d] must be positive and finite", a);
+    }
+    if (g->nbl > 0) {
+        if (g->damp_power < 1 || g->damp_power > 4) return fail(AWE_EINVAL, "damp_power must be in 1..4");
+        if (!(g->damp_R > 0.0 && g->damp_R < 1.0)) return fail(AWE_EINVAL, "damp_R must be in (0, 1)");
+        if (!(g->damp_vref > 0.0) || !std::isfinite(g->damp_vref)) return fail(AWE_EINVAL, "damp_vref must be > 0");
+    }
+    if (!(g->dt > 0.0) || !std::isfinite(g->dt)) return fail(AWE_EINVAL, "dt must be positive and finite");
+    if (g->nt < 1) return fail(AWE_EINVAL, "nt must be >= 1 (got %d)", g->nt);
+    if (g->nsrc < 0 || g->nrec < 0) return fail(AWE_EINVAL, "nsrc and nrec must be >= 0");
+    if (g->nsrc > 0 && !g->src_coords) return fail(AWE_EINVAL, "src_coords is NULL");
+    if (g->nrec > 0 && !g->rec_coords) return fail(AWE_EINVAL, "rec_coords is NULL");
+    if (g->reserved != 0) return fail(AWE_EINVAL, "reserved field must be 0");
+    int64_t pts = 1;
+    for (int a = 0; a < g->ndim; ++a) pts *= g->shape[a] + 2 * (int64_t)g->nbl;
+    if (pts > (int64_t(1) << 33)) return fail(AWE_EINVAL, "padded grid too large");
+    if ((int64_t)g->nt * std::max(g->nrec, g->nsrc) > (int64_t(1) << 34))
+        return fail(AWE_EINVAL, "trace arrays too large");
+    return AWE_OK;
+}
+
+// Padded extents in (z, y, x) order; y = 1 in 2-D.
+void padded_zyx(const awe_geometry* g, int64_t pad[3], int64_t phys[3]) {
+    if (g->ndim == 3) {
+        for (int a = 0; a < 3; ++a) { phys[a] = g->shape[a]; pad[a] = g->shape[a] + 2 * (int64_t)g->nbl; }
+    } else {
+        phys[0] = g->shape[0]; phys[1] = 1; phys[2] = g->shape[1];
+        pad[0] = phys[0] + 2 * (int64_t)g->nbl; pad[1] = 1; pad[2] = phys[2] + 2 * (int64_t)g->nbl;
+    }
+}
+
+Layout make_layout(int ndim, const int64_t pad[3], int half) {
+    Layout L;
+    L.ndim = ndim;
+    L.half = half;
+    for (int a = 0; a < 3; ++a) L.n[a] = pad[a];
+    const int64_t px = ((kXOff + pad[2] + half) + 31) / 32 * 32;
+    const int64_t py = ndim == 3 ? pad[1] + 2 * half : 1;
+    const int64_t yo = ndim == 3 ? half : 0;
+    const int64_t pz = pad[0] + 2 * half;
+    L.sy = px;
+    L.sz = px * py;
+    L.origin = half * L.sz + yo * L.sy + kXOff;
+    L.total = pz * L.sz;
+    return L;
+}
+
+// Times t whose wavefield the checkpointed forward keeps: the pairs
+// (u[jK], u[jK-1]) for j = 1 .. S-1 (S = ceil(nt/K)); u[0] = u[-1] = 0 need no storage.
+std::vector<int> stored_times(int nt, int K) {
+    std::set<int> t;
+    const int S = (nt + K - 1) / K;
+    for (int j = 1; j < S; ++j) {
+        if (j * K >= 1 && j * K <= nt - 1) t.insert(j * K);
+        if (j * K - 1 >= 1 && j * K - 1 <= nt - 1) t.insert(j * K - 1);
+    }
+    return std::vector<int>(t.begin(), t.end());
+}
+
+int segment_slots(int nt, int K) { return std::max(0, std::min(K - 1, nt - 1)); }
+
+uint64_t footprint_bytes(const awe_geometry* g, int K) {
+    int64_t pad[3], phys[3];
+    padded_zyx(g, pad, phys);
+    const Layout L = make_layout(g->ndim, pad, g->space_order / 2);
+    const uint64_t field = (uint64_t)L.total * 4;
+    const int corners = 1 << g->ndim;
+    uint64_t b = 3 * field;                                                    // C, two wavefields
+    b += (uint64_t)(pad[0] + pad[1] + pad[2]) * 12;                            // eta tables (fp32 + fp64)
+    b += (uint64_t)(g->nsrc + g->nrec) * corners * (8 + 4) * 2 + 8 * corners * (g->nsrc + g->nrec + 2);
+    b += 64 * 1024;                                                            // reduction scratch
+    if (K > 0) {
+        b += (uint64_t)(stored_times(g->nt, K).size() + segment_slots(g->nt, K) + 3) * field;  // + mu x2, g
+        b += (uint64_t)g->nt * g->nsrc * 4;                                    // wavelet copy
+    }
+    return b;
+}
+
+// ---------------------------------------------------------------------------
+// damping tables and off-grid point tables
+// ---------------------------------------------------------------------------
+std::vector<double> damping_axis(int64_t n, int nbl, double h, int power, double R, double vref) {
+    std::vector<double> e(n + 2 * nbl, 0.0);
+    if (nbl == 0) return e;
+    const double emax = (power + 1) * std::log(1.0 / R) / (vref * nbl * h);
+    for (int64_t i = 0; i < n + 2 * nbl; ++i) {
+        const int64_t d = std::max<int64_t>({int64_t(nbl) - i, i - (n + nbl - 1), 0});
+        e[i] = emax * std::pow(double(d) / nbl, power);
+    }
+    return e;
+}
+
+struct PointTable {
+    std::vector<int64_t> node;   // [npts][corners] pitched indices
+    std::vector<float> w;        // [npts][corners]
+};
+
+static awe_status build_points(const awe_geometry* g, const Layout& L, const double* coords, int npts,
+                               const char* what, PointTable& out) {
+    const int d = g->ndim;
+    const int corners = 1 << d;
+    out.node.resize((size_t)npts * corners);
+    out.w.resize((size_t)npts * corners);
+    int64_t padn[3];
+    for (int a = 0; a < d; ++a) padn[a] = g->shape[a] + 2 * (int64_t)g->nbl;
+    for (int p = 0; p < npts; ++p) {
+        int64_t i0[3];
+        double f[3];
+        for (int a = 0; a < d; ++a) {
+            const double s = coords[(size_t)p * d + a] / g->spacing[a] + g->nbl;
+            if (!std::isfinite(s) || s < 0.0 || s > double(padn[a] - 1))
+                return fail(AWE_EINVAL, "%s %d lies outside the padded grid on axis %d", what, p, a);
+            int64_t b = (int64_t)std::floor(s);
+            if (b > padn[a] - 2) b = padn[a] - 2;
+            i0[a] = b;
+            f[a] = s - double(b);
+        }
+        for (int c = 0; c < corners; ++c) {
+            int64_t idx[3] = {0, 0, 0};
+            double w = 1.0;
+            for (int a = 0; a < d; ++a) {
+                const int bit = (c >> (d - 1 - a)) & 1;   // axis 0 is the slowest bit
+                idx[a] = i0[a] + bit;
+                w *= bit ? f[a] : (1.0 - f[a]);
+            }
+            const int64_t lin = d == 3 ? L.index(idx[0], idx[1], idx[2]) : L.index(idx[0], 0, idx[1]);
+            out.node[(size_t)p * corners + c] = lin;
+            out.w[(size_t)p * corners + c] = (float)w;
+        }
+    }
+    return AWE_OK;
+}
+
+struct CsrHost {
+    std::vector<int64_t> node;
+    std::vector<int32_t> rowptr, pt;
+    std::vector<float> w;
+};
+
+// Group the (node, point, weight) triples by node, ascending node then point,
+// so injection is a deterministic gather.
+static CsrHost build_csr(const PointTable& t, int npts, int corners) {
+    std::vector<std::pair<int64_t, int32_t>> keys;
+    keys.reserve((size_t)npts * corners);
+    for (int p = 0; p < npts; ++p)
+        for (int c = 0; c < corners; ++c) keys.push_back({t.node[(size_t)p * corners + c], p * corners + c});
+    std::sort(keys.begin(), keys.end());
+    CsrHost h;
+    for (size_t i = 0; i < keys.size(); ++i) {
+        if (i == 0 || keys[i].first != keys[i - 1].first) {
+            h.node.push_back(keys[i].first);
+            h.rowptr.push_back((int32_t)h.pt.size());
+        }
+        h.pt.push_back(keys[i].second / corners);
+        h.w.push_back(t.w[keys[i].second]);
+    }
+    h.rowptr.push_back((int32_t)h.pt.size());
+    return h;
+}
+
+}  // namespace awe
+
+using namespace awe;
+using Plan = awe_plan_s;
+
+// ---------------------------------------------------------------------------
+// device memory helpers
+// ---------------------------------------------------------------------------
+awe_status Plan::alloc(void** p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) return AWE_OK;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return fail(AWE_ENOMEM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+    }
+    owned.push_back(*p);
+    held += bytes;
+    return AWE_OK;
+}
+
+awe_status Plan::alloc_field(float** p) {
+    awe_status st = alloc((void**)p, (size_t)L.total * sizeof(float));
+    if (st) return st;
+    // zero once: the ghost cells must stay zero for the plan's lifetime
+    AWE_HIP(launch_fill(*p, L.total, 0.f, nullptr));
+    return AWE_OK;
+}
+
+template <class T>
+awe_status Plan::upload(T** dst, const std::vector<T>& v) {
+    awe_status st = alloc((void**)dst, v.size() * sizeof(T));
+    if (st) return st;
+    if (!v.empty()) AWE_HIP(hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return AWE_OK;
+}
+
+void Plan::release(void* p) {
+    if (!p) return;
+    auto it = std::find(owned.begin(), owned.end(), p);
+    if (it != owned.end()) owned.erase(it);
+    (void)hipFree(p);
+}
+
+Plan::~awe_plan_s() {
+    for (void* p : owned) (void)hipFree(p);
+}
+
+awe_status Plan::init(const awe_geometry* geo) {
+    g = *geo;
+    src.assign(geo->src_coords, geo->src_coords + (size_t)geo->nsrc * geo->ndim);
+    rec.assign(geo->rec_coords, geo->rec_coords + (size_t)geo->nrec * geo->ndim);
+    g.src_coords = src.data();
+    g.rec_coords = rec.data();
+    half = g.space_order / 2;
+    corners = 1 << g.ndim;
+    padded_zyx(&g, pad, phys);
+    L = make_layout(g.ndim, pad, half);
+    vol = 1.0;
+    for (int a = 0; a < g.ndim; ++a) vol *= g.spacing[a];
+
+    // stencil coefficients, axis order (z, y, x)
+    double c[kMaxHalf + 1];
+    fd_weights(g.space_order, c);
+    double hz = g.spacing[0], hy = g.ndim == 3 ? g.spacing[1] : 0.0, hx = g.spacing[g.ndim - 1];
+    std::memset(&k, 0, sizeof k);
+    double inv_sum = 1.0 / (hz * hz) + 1.0 / (hx * hx) + (g.ndim == 3 ? 1.0 / (hy * hy) : 0.0);
+    k.c0 = (float)(c[0] * inv_sum);
+    for (int j = 1; j <= half; ++j) {
+        k.cz[j] = (float)(c[j] / (hz * hz));
+        k.cx[j] = (float)(c[j] / (hx * hx));
+        k.cy[j] = g.ndim == 3 ? (float)(c[j] / (hy * hy)) : 0.f;
+    }
+    k.inv_dt = (float)(1.0 / g.dt);
+
+    // launch shape: AWE_TILE="cfg,zchunk" overrides the default
+    tile_cfg = 0;
+    if (g.ndim == 3) {
+        const int64_t tiles = ((pad[2] + kTileX - 1) / kTileX) * ((pad[1] + tile_rows(3, 0) - 1) / tile_rows(3, 0));
+        const int64_t want = std::max<int64_t>(1, (2048 + tiles - 1) / tiles);
+        zchunk = (int)std::max<int64_t>(16, (pad[0] + want - 1) / want);
+    } else {
+        zchunk = 32;
+    }
+    if (const char* env = std::getenv("AWE_TILE")) {
+        int cfg = -1, zc = -1;
+        if (std::sscanf(env, "%d,%d", &cfg, &zc) == 2 && cfg >= 0 && cfg < num_tile_cfgs(g.ndim) && zc > 0) {
+            tile_cfg = cfg;
+            zchunk = zc;
+        }
+    }
+
+    // damping tables
+    std::vector<double> ez, ey, ex;
+    if (g.ndim == 3) {
+        ez = damping_axis(g.shape[0], g.nbl, g.spacing[0], g.damp_power, g.damp_R, g.damp_vref);
+        ey = damping_axis(g.shape[1], g.nbl, g.spacing[1], g.damp_power, g.damp_R, g.damp_vref);
+        ex = damping_axis(g.shape[2], g.nbl, g.spacing[2], g.damp_power, g.damp_R, g.damp_vref);
+    } else {
+        ez = damping_axis(g.shape[0], g.nbl, g.spacing[0], g.damp_power, g.damp_R, g.damp_vref);
+        ey.assign(1, 0.0);
+        ex = damping_axis(g.shape[1], g.nbl, g.spacing[1], g.damp_power, g.damp_R, g.damp_vref);
+    }
+    auto tof = [](const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); };
+
+    // off-grid tables
+    PointTable ts, tr;
+    awe_status st;
+    if ((st = build_points(&g, L, src.data(), g.nsrc, "source", ts))) return st;
+    if ((st = build_points(&g, L, rec.data(), g.nrec, "receiver", tr))) return st;
+    CsrHost cs = build_csr(ts, g.nsrc, corners);
+    CsrHost cr = build_csr(tr, g.nrec, corners);
+
+    int dev = 0;
+    AWE_HIP(hipGetDevice(&dev));
+    device = dev;
+    if ((st = upload(&d_ezd, ez)) || (st = upload(&d_eyd, ey)) || (st = upload(&d_exd, ex))) return st;
+    if ((st = upload(&d_ez, tof(ez))) || (st = upload(&d_ey, tof(ey))) || (st = upload(&d_ex, tof(ex)))) return st;
+    if ((st = upload(&src_node, ts.node)) || (st = upload(&src_w, ts.w))) return st;
+    if ((st = upload(&rec_node, tr.node)) || (st = upload(&rec_w, tr.w))) return st;
+    if ((st = upload(&src_csr.node, cs.node)) || (st = upload(&src_csr.rowptr, cs.rowptr)) ||
+        (st = upload(&src_csr.pt, cs.pt)) || (st = upload(&src_csr.w, cs.w)))
+        return st;
+    src_csr.nrows = (int32_t)cs.node.size();
+    if ((st = upload(&rec_csr.node, cr.node)) || (st = upload(&rec_csr.rowptr, cr.rowptr)) ||
+        (st = upload(&rec_csr.pt, cr.pt)) || (st = upload(&rec_csr.w, cr.w)))
+        return st;
+    rec_csr.nrows = (int32_t)cr.node.size();
+    if ((st = alloc_field(&coef)) || (st = alloc_field(&w0)) || (st = alloc_field(&w1))) return st;
+    if ((st = alloc((void**)&d_partial, 3 * 4096 * sizeof(float)))) return st;
+    if ((st = alloc((void**)&d_mpart, (kReduceBlocks + 1) * sizeof(double)))) return st;
+    AWE_HIP(hipDeviceSynchronize());
+    cur = w0;
+    prev = w1;
+    return AWE_OK;
+}
+
+awe_status Plan::set_model(const float* m, hipStream_t s) {
+    if (!m) return fail(AWE_EINVAL, "model pointer is NULL");
+    const int64_t n = phys[0] * phys[1] * phys[2];
+    const int blocks = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (n + 255) / 256));
+    AWE_HIP(launch_minmax(m, n, d_partial, blocks, s));
+    std::vector<float> part(3 * (size_t)blocks);
+    AWE_HIP(hipMemcpyAsync(part.data(), d_partial, part.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+    AWE_HIP(hipStreamSynchronize(s));
+    float lo = INFINITY, hi = -INFINITY, bad = 0.f;
+    for (int b = 0; b < blocks; ++b) {
+        lo = std::min(lo, part[3 * b]);
+        hi = std::max(hi, part[3 * b + 1]);
+        bad += part[3 * b + 2];
+    }
+    if (bad > 0.f) return fail(AWE_EUNSTABLE, "model has %.0f non-finite values", bad);
+    if (!(lo > 0.f)) return fail(AWE_EUNSTABLE, "squared slowness must be positive (min %g)", lo);
+    const double vmax = std::sqrt(1.0 / (double)lo);
+    const double lim = dt_limit(g.ndim, g.space_order, g.spacing, vmax);
+    if (g.dt > lim) return fail(AWE_EUNSTABLE, "dt = %g exceeds the stability limit %g (v_max = %g)", g.dt, lim, vmax);
+    AWE_HIP(launch_coef(coef, m, L, phys, g.nbl, d_ezd, d_eyd, d_exd, g.dt, s));
+    model_set = true;
+    have_ckpt = false;
+    have_grad = false;
+    return AWE_OK;
+}
+
+// One step of the recurrence from (uc, up) into out, then the point source.
+awe_status Plan::advance(const float* uc, const float* up, float* out, const float* q_row, hipStream_t s) {
+    StepArgs a{uc, up, out, coef, d_ez, d_ey, d_ex, nullptr, nullptr};
+    AWE_HIP(launch_step(L, k, a, false, tile_cfg, zchunk, s));
+    if (q_row && g.nsrc > 0)
+        AWE_HIP(launch_inject(out, coef, src_csr.node, src_csr.rowptr, src_csr.pt, src_csr.w, src_csr.nrows, q_row,
+                              (float)(1.0 / vol), nullptr, nullptr, s));
+    return AWE_OK;
+}
+
+awe_status Plan::ensure_gradient_storage(int K) {
+    if (K == ckpt_K && storage_ready) return AWE_OK;
+    storage_ready = false;
+    // (re)allocate for a new K
+    for (auto& kv : stored) release(kv.second);
+    stored.clear();
+    for (float* p : slots) release(p);
+    slots.clear();
+    awe_status st;
+    for (int t : stored_times(g.nt, K)) {
+        float* p = nullptr;
+        if ((st = alloc_field(&p))) return st;
+        stored[t] = p;
+    }
+    for (int i = 0; i < segment_slots(g.nt, K); ++i) {
+        float* p = nullptr;
+        if ((st = alloc_field(&p))) return st;
+        slots.push_back(p);
+    }
+    if (!mu0 && ((st = alloc_field(&mu0)) || (st = alloc_field(&mu1)) || (st = alloc_field(&grad)))) return st;
+    if (!wavelet_copy && g.nsrc > 0 && (st = alloc((void**)&wavelet_copy, (size_t)g.nt * g.nsrc * sizeof(float))))
+        return st;
+    ckpt_K = K;
+    AWE_HIP(hipDeviceSynchronize());
+    storage_ready = true;
+    return AWE_OK;
+}
+
+awe_status Plan::forward(const float* wavelet, float* traces, int K, hipStream_t s) {
+    if (!model_set) return fail(AWE_ESTATE, "awe_set_model has not been called on this plan");
+    if (g.nsrc > 0 && !wavelet) return fail(AWE_EINVAL, "wavelet is NULL but nsrc > 0");
+    if (K < 0) return fail(AWE_EINVAL, "ckpt_every must be >= 0");
+    awe_status st;
+    have_ckpt = false;
+    if (K > 0) {
+        if ((st = ensure_gradient_storage(K))) return st;
+        if (g.nsrc > 0)
+            AWE_HIP(hipMemcpyAsync(wavelet_copy, wavelet, (size_t)g.nt * g.nsrc * sizeof(float),
+                                   hipMemcpyDeviceToDevice, s));
+    }
+    AWE_HIP(launch_fill(w0, L.total, 0.f, s));
+    AWE_HIP(launch_fill(w1, L.total, 0.f, s));
+    if (traces && g.nrec > 0) AWE_HIP(launch_fill(traces, g.nrec, 0.f, s));
+    cur = w0;
+    prev = w1;
+    for (int n = 0; n + 1 < g.nt; ++n) {
+        float* dst = nullptr;
+        if (K > 0) {
+            auto it = stored.find(n + 1);
+            if (it != stored.end()) dst = it->second;
+        }
+        if (!dst) dst = pick_work_dst();
+        if ((st = advance(cur, prev, dst, g.nsrc ? wavelet + (size_t)n * g.nsrc : nullptr, s))) return st;
+        if (traces && g.nrec > 0)
+            AWE_HIP(launch_sample(traces + (size_t)(n + 1) * g.nrec, dst, rec_node, rec_w, g.nrec, corners, 1.f, s));
+        prev = cur;
+        cur = dst;
+    }
+    have_ckpt = K > 0;
+    return AWE_OK;
+}
+
+float* Plan::pick_work_dst() {
+    if (prev == w0 || prev == w1) return const_cast<float*>(prev);   // in place over u[n-1]
+    return cur == w0 ? w1 : w0;
+}
+
+awe_status Plan::step(int n0, int nsteps, const float* wavelet, float* traces, hipStream_t s) {
+    if (!model_set) return fail(AWE_ESTATE, "awe_set_model has not been called on this plan");
+    if (n0 < 0 || nsteps < 0 || (int64_t)n0 + nsteps > (int64_t)g.nt - 1)
+        return fail(AWE_EINVAL, "steps %d..%d exceed nt-1 = %d", n0, n0 + nsteps, g.nt - 1);
+    awe_status st;
+    for (int n = n0; n < n0 + nsteps; ++n) {
+        float* dst = pick_work_dst();
+        if ((st = advance(cur, prev, dst, (wavelet && g.nsrc) ? wavelet + (size_t)n * g.nsrc : nullptr, s))) return st;
+        if (traces && g.nrec > 0)
+            AWE_HIP(launch_sample(traces + (size_t)(n + 1) * g.nrec, dst, rec_node, rec_w, g.nrec, corners, 1.f, s));
+        prev = cur;
+        cur = dst;
+    }
+    return AWE_OK;
+}
+
+awe_status Plan::adjoint(const float* resid, float* src_adj, float* grad_phys, hipStream_t s) {
+    if (!model_set) return fail(AWE_ESTATE, "awe_set_model has not been called on this plan");
+    if (g.nrec > 0 && !resid) return fail(AWE_EINVAL, "resid is NULL but nrec > 0");
+    const bool want_grad = grad_phys != nullptr;
+    if (want_grad && !have_ckpt)
+        return fail(AWE_ESTATE, "a gradient needs a preceding awe_forward with ckpt_every > 0");
+    awe_status st;
+    if (!mu0 && ((st = alloc_field(&mu0)) || (st = alloc_field(&mu1)))) return st;
+    if (want_grad && !grad && (st = alloc_field(&grad))) return st;
+    AWE_HIP(launch_fill(mu0, L.total, 0.f, s));
+    AWE_HIP(launch_fill(mu1, L.total, 0.f, s));
+    if (want_grad) AWE_HIP(launch_fill(grad, L.total, 0.f, s));
+    if (src_adj && g.nsrc > 0) AWE_HIP(launch_fill(src_adj + (size_t)(g.nt - 1) * g.nsrc, g.nsrc, 0.f, s));
+    float* m1 = mu0;   // mu[n+1]
+    float* m2 = mu1;   // mu[n+2]
+    const float inv_vol = (float)(1.0 / vol);
+
+    auto adj_step = [&](int n, const float* usnap) -> awe_status {
+        if (src_adj && g.nsrc > 0 && n <= g.nt - 2)
+            AWE_HIP(launch_sample(src_adj + (size_t)n * g.nsrc, m1, src_node, src_w, g.nsrc, corners, inv_vol, s));
+        const bool img = usnap != nullptr;
+        StepArgs a{m1, m2, m2, coef, d_ez, d_ey, d_ex, usnap, img ? grad : nullptr};
+        AWE_HIP(launch_step(L, k, a, img, tile_cfg, zchunk, s));
+        if (g.nrec > 0)
+            AWE_HIP(launch_inject(m2, coef, rec_csr.node, rec_csr.rowptr, rec_csr.pt, rec_csr.w, rec_csr.nrows,
+                                  resid + (size_t)n * g.nrec, 1.f, usnap, img ? grad : nullptr, s));
+        std::swap(m1, m2);
+        return AWE_OK;
+    };
+
+    if (!want_grad) {
+        for (int n = g.nt - 1; n >= 0; --n)
+            if ((st = adj_step(n, nullptr))) return st;
+        have_grad = false;
+        return AWE_OK;
+    }
+
+    // Reverse sweep over segments [jK, min(jK+K, nt) - 1], j = S-1 .. 0.
+    const int K = ckpt_K;
+    const int S = (g.nt + K - 1) / K;
+    float* zero = w0;                         // u[0] = u[-1] = 0
+    AWE_HIP(launch_fill(zero, L.total, 0.f, s));
+    const float* qsrc = g.nsrc ? wavelet_copy : nullptr;
+    std::vector<const float*> ptr;            // ptr[t - (t0 - 1)] = u[t]
+    for (int j = S - 1; j >= 0; --j) {
+        const int t0 = j * K;
+        const int t1 = std::min(t0 + K, g.nt) - 1;
+        ptr.assign(t1 - t0 + 2, nullptr);
+        auto at = [&](int t) -> const float*& { return ptr[t - (t0 - 1)]; };
+        for (int t = t0 - 1; t <= t1; ++t) {
+            if (t <= 0) at(t) = zero;
+            else {
+                auto it = stored.find(t);
+                at(t) = it != stored.end() ? it->second : nullptr;
+            }
+        }
+        int slot = 0;
+        for (int t = t0 + 1; t <= t1; ++t) {
+            if (at(t)) continue;
+            float* dst = slots[slot++];
+            if ((st = advance(at(t - 1), at(t - 2), dst, qsrc ? qsrc + (size_t)(t - 1) * g.nsrc : nullptr, s)))
+                return st;
+            at(t) = dst;
+        }
+        for (int n = t1; n >= t0; --n)
+            if ((st = adj_step(n, n >= 1 ? at(n) : nullptr))) return st;
+    }
+    // g_phys = fold(-(1/dt^2) * accumulated imaging)
+    AWE_HIP(launch_fold(grad_phys, grad, L, phys, g.nbl, (float)(-1.0 / (g.dt * g.dt)), s));
+    have_grad = true;
+    return AWE_OK;
+}
+
+

@@ -1,0 +1,265 @@
+// Off-grid point operators, coefficient build, gradient fold and reductions.
+#include "awe_internal.hpp"
+
+namespace awe {
+namespace {
+
+constexpr int kBlock = 256;
+
+inline unsigned blocks_for(int64_t n, int64_t cap = 65535 * 8) {
+    int64_t b = (n + kBlock - 1) / kBlock;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (unsigned)b;
+}
+
+// Source injection (Sec. IV sparse-point insertion; the transpose of the
+// multilinear interpolation).  One thread per touched grid node: the node's
+// CSR row lists (point, weight) pairs in ascending point order, so the sum is
+// deterministic and no atomics are needed.
+//   field[node] += C[node] * scale * sum_e w_e values[pt_e]
+//   imaging:  grad[node] += usnap[node] * (that same increment)
+__global__ void __launch_bounds__(kBlock)
+inject_k(float* field, const float* coef, const int64_t* node, const int32_t* rowptr, const int32_t* pt,
+         const float* w, int32_t nrows, const float* values, float scale, const float* usnap, float* grad) {
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= nrows) return;
+    float s = 0.f;
+    for (int e = rowptr[j]; e < rowptr[j + 1]; ++e) s += w[e] * values[pt[e]];
+    const int64_t i = node[j];
+    const float inc = coef[i] * (s * scale);
+    field[i] += inc;
+    if (grad) grad[i] += usnap[i] * inc;
+}
+
+// Receiver interpolation: out[r] = scale * sum_k w[r][k] field[node[r][k]].
+__global__ void __launch_bounds__(kBlock)
+sample_k(float* out, const float* field, const int64_t* node, const float* w, int32_t npts, int32_t corners,
+         float scale) {
+    const int r = blockIdx.x * kBlock + threadIdx.x;
+    if (r >= npts) return;
+    float s = 0.f;
+    for (int k = 0; k < corners; ++k) s += w[(int64_t)r * corners + k] * field[node[(int64_t)r * corners + k]];
+    out[r] = s * scale;
+}
+
+struct PadGeo {
+    int64_t n0, n1, n2;          // padded extents
+    int64_t p0, p1, p2;          // physical extents
+    int64_t sy, sz, origin;
+    int nbl;
+};
+
+__device__ __forceinline__ int64_t clampi(int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// C = dt^2 / (m + eta dt / 2) on the padded grid, in FP64 then rounded once.
+// The absorbing layer takes m from the nearest physical edge cell.
+__global__ void __launch_bounds__(kBlock)
+coef_k(float* coef, const float* m, PadGeo g, const double* ez, const double* ey, const double* ex, double dt) {
+    const int64_t total = g.n0 * g.n1 * g.n2;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (int64_t)gridDim.x * kBlock) {
+        const int64_t x = i % g.n2;
+        const int64_t y = (i / g.n2) % g.n1;
+        const int64_t z = i / (g.n2 * g.n1);
+        const int64_t pz = clampi(z - g.nbl, 0, g.p0 - 1);
+        const int64_t py = g.p1 > 1 ? clampi(y - g.nbl, 0, g.p1 - 1) : 0;
+        const int64_t px = clampi(x - g.nbl, 0, g.p2 - 1);
+        const double mv = (double)m[(pz * g.p1 + py) * g.p2 + px];
+        const double eta = ez[z] + ey[y] + ex[x];
+        coef[g.origin + z * g.sz + y * g.sy + x] = (float)(dt * dt / (mv + 0.5 * eta * dt));
+    }
+}
+
+// Per-block min, max and non-finite count of the model (fixed block order).
+__global__ void __launch_bounds__(kBlock)
+minmax_k(const float* m, int64_t n, float* partial) {
+    __shared__ float smin[kBlock], smax[kBlock], sbad[kBlock];
+    float lo = INFINITY, hi = -INFINITY, bad = 0.f;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        const float v = m[i];
+        if (!isfinite(v)) bad += 1.f;
+        else { lo = fminf(lo, v); hi = fmaxf(hi, v); }
+    }
+    smin[threadIdx.x] = lo; smax[threadIdx.x] = hi; sbad[threadIdx.x] = bad;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            smin[threadIdx.x] = fminf(smin[threadIdx.x], smin[threadIdx.x + s]);
+            smax[threadIdx.x] = fmaxf(smax[threadIdx.x], smax[threadIdx.x + s]);
+            sbad[threadIdx.x] += sbad[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[3 * blockIdx.x + 0] = smin[0];
+        partial[3 * blockIdx.x + 1] = smax[0];
+        partial[3 * blockIdx.x + 2] = sbad[0];
+    }
+}
+
+// Adjoint of the edge-replication padding, scaled: every physical cell gets
+// scale * (sum of the padded cells that copy it), summed in FP64 in a fixed
+// order.  Interior cells map to one padded cell; edge cells gather the layer.
+__global__ void __launch_bounds__(kBlock)
+fold_k(float* grad, const float* g, PadGeo p, float scale) {
+    const int64_t total = p.p0 * p.p1 * p.p2;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (int64_t)gridDim.x * kBlock) {
+        const int64_t x = i % p.p2;
+        const int64_t y = (i / p.p2) % p.p1;
+        const int64_t z = i / (p.p2 * p.p1);
+        const int64_t z_lo = (z == 0) ? 0 : z + p.nbl, z_hi = (z == p.p0 - 1) ? p.n0 - 1 : z + p.nbl;
+        int64_t y_lo = 0, y_hi = 0;
+        if (p.p1 > 1) {
+            y_lo = (y == 0) ? 0 : y + p.nbl;
+            y_hi = (y == p.p1 - 1) ? p.n1 - 1 : y + p.nbl;
+        }
+        const int64_t x_lo = (x == 0) ? 0 : x + p.nbl, x_hi = (x == p.p2 - 1) ? p.n2 - 1 : x + p.nbl;
+        double s = 0.0;
+        for (int64_t zz = z_lo; zz <= z_hi; ++zz)
+            for (int64_t yy = y_lo; yy <= y_hi; ++yy) {
+                const float* row = g + p.origin + zz * p.sz + yy * p.sy;
+                for (int64_t xx = x_lo; xx <= x_hi; ++xx) s += (double)row[xx];
+            }
+        grad[i] = (float)(s * (double)scale);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
+pack_k(float* dense, const float* pitched, PadGeo g, float scale) {
+    const int64_t total = g.n0 * g.n1 * g.n2;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (int64_t)gridDim.x * kBlock) {
+        const int64_t x = i % g.n2;
+        const int64_t y = (i / g.n2) % g.n1;
+        const int64_t z = i / (g.n2 * g.n1);
+        dense[i] = scale * pitched[g.origin + z * g.sz + y * g.sy + x];
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
+unpack_k(float* pitched, const float* dense, PadGeo g) {
+    const int64_t total = g.n0 * g.n1 * g.n2;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (int64_t)gridDim.x * kBlock) {
+        const int64_t x = i % g.n2;
+        const int64_t y = (i / g.n2) % g.n1;
+        const int64_t z = i / (g.n2 * g.n1);
+        pitched[g.origin + z * g.sz + y * g.sy + x] = dense[i];
+    }
+}
+
+// Residual and per-block FP64 partial sums of its square (fixed order).
+__global__ void __launch_bounds__(kBlock)
+misfit_k(const float* tr, const float* obs, int64_t n, float* resid, double* partial) {
+    __shared__ double sh[kBlock];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        const float r = tr[i] - obs[i];
+        if (resid) resid[i] = r;
+        acc += (double)r * (double)r;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(kBlock)
+sum_partials_k(const double* partial, int nparts, double* result) {
+    __shared__ double sh[kBlock];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += kBlock) acc += partial[i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *result = 0.5 * sh[0];
+}
+
+__global__ void __launch_bounds__(kBlock)
+fill_k(float* p, int64_t n, float v) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) p[i] = v;
+}
+
+PadGeo pad_geo(const Layout& L, const int64_t phys[3], int nbl) {
+    PadGeo g;
+    g.n0 = L.n[0]; g.n1 = L.n[1]; g.n2 = L.n[2];
+    g.p0 = phys ? phys[0] : L.n[0];
+    g.p1 = phys ? phys[1] : L.n[1];
+    g.p2 = phys ? phys[2] : L.n[2];
+    g.sy = L.sy; g.sz = L.sz; g.origin = L.origin;
+    g.nbl = nbl;
+    return g;
+}
+
+}  // namespace
+
+hipError_t launch_inject(float* field, const float* coef, const int64_t* node, const int32_t* rowptr,
+                         const int32_t* pt, const float* w, int32_t nrows, const float* values, float scale,
+                         const float* usnap, float* grad, hipStream_t s) {
+    if (nrows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(inject_k, dim3(blocks_for(nrows)), dim3(kBlock), 0, s, field, coef, node, rowptr, pt, w,
+                       nrows, values, scale, usnap, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample(float* out, const float* field, const int64_t* node, const float* w, int32_t npts,
+                         int32_t corners, float scale, hipStream_t s) {
+    if (npts <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sample_k, dim3(blocks_for(npts)), dim3(kBlock), 0, s, out, field, node, w, npts, corners,
+                       scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_coef(float* coef, const float* m_phys, const Layout& L, const int64_t phys[3], int nbl,
+                       const double* eta_z, const double* eta_y, const double* eta_x, double dt, hipStream_t s) {
+    PadGeo g = pad_geo(L, phys, nbl);
+    hipLaunchKernelGGL(coef_k, dim3(blocks_for(L.points(), 8192)), dim3(kBlock), 0, s, coef, m_phys, g, eta_z, eta_y,
+                       eta_x, dt);
+    return hipGetLastError();
+}
+
+hipError_t launch_minmax(const float* m, int64_t n, float* partial, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL(minmax_k, dim3(blocks), dim3(kBlock), 0, s, m, n, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold(float* grad_phys, const float* g, const Layout& L, const int64_t phys[3], int nbl,
+                       float scale, hipStream_t s) {
+    PadGeo p = pad_geo(L, phys, nbl);
+    hipLaunchKernelGGL(fold_k, dim3(blocks_for(p.p0 * p.p1 * p.p2, 8192)), dim3(kBlock), 0, s, grad_phys, g, p,
+                       scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(float* dense, const float* pitched, const Layout& L, float scale, hipStream_t s) {
+    PadGeo g = pad_geo(L, nullptr, 0);
+    hipLaunchKernelGGL(pack_k, dim3(blocks_for(L.points(), 8192)), dim3(kBlock), 0, s, dense, pitched, g, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack(float* pitched, const float* dense, const Layout& L, hipStream_t s) {
+    PadGeo g = pad_geo(L, nullptr, 0);
+    hipLaunchKernelGGL(unpack_k, dim3(blocks_for(L.points(), 8192)), dim3(kBlock), 0, s, pitched, dense, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_misfit(const float* tr, const float* obs, int64_t n, float* resid, double* partial, int blocks,
+                         double* result, hipStream_t s) {
+    hipLaunchKernelGGL(misfit_k, dim3(blocks), dim3(kBlock), 0, s, tr, obs, n, resid, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sum_partials_k, dim3(1), dim3(kBlock), 0, s, partial, blocks, result);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_k, dim3(blocks_for(n, 16384)), dim3(kBlock), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+}  // namespace awe

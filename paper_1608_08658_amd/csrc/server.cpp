@@ -1,0 +1,333 @@
+// Shot server with continuous batching (extern "C" awe_server_* of awe.h).
+//
+// Requests are admitted against a device-memory budget and a cap on running
+// requests.  The engine thread runs iterations: each iteration enqueues up to
+// `chunk` time steps of every running request on that request's own stream,
+// so the kernels of different shots overlap on the device, and a request
+// that arrives while others run joins at the next iteration boundary instead
+// of waiting for the batch to drain.  Finished requests are retired (traces
+// copied out, memory released) as soon as their stream reaches the end, which
+// frees budget for the queue.  Each request's arithmetic is exactly that of a
+// plan run alone: the steps are the same kernels on the same data, only
+// interleaved in time with other requests.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "awe.h"
+#include "engine.hpp"
+
+using awe::fail;
+
+namespace {
+
+double now_s(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+struct Request {
+    int64_t id = 0;
+    awe_geometry g{};
+    std::vector<double> src, rec;
+    std::vector<float> m, wavelet;
+    float* traces_host = nullptr;
+    uint64_t bytes = 0;
+    int state = AWE_REQ_QUEUED;
+    double t[4] = {-1, -1, -1, -1};
+    std::string err;
+    // device side while running
+    awe_plan plan = nullptr;
+    hipStream_t stream = nullptr;
+    hipEvent_t chunk_done = nullptr;
+    float* d_m = nullptr;
+    float* d_wav = nullptr;
+    float* d_tr = nullptr;
+    int next = 0;             // next step index n (u[n+1] is produced next)
+    bool copying = false;     // traces copy-out enqueued
+};
+
+}  // namespace
+
+struct awe_server_s {
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    int device = 0;
+    int chunk = 64;
+    int max_active = 8;
+    uint64_t budget = 0;
+    uint64_t reserved = 0;
+    int64_t next_id = 0;
+    int64_t n_submitted = 0, n_admitted = 0, n_completed = 0, n_failed = 0, iterations = 0;
+    std::mutex mu;
+    std::condition_variable wake;     // engine: new work or stop
+    std::condition_variable changed;  // waiters: a request changed state
+    std::deque<Request*> queue;
+    std::vector<Request*> active;
+    std::map<int64_t, std::unique_ptr<Request>> all;
+    bool stop = false;
+    std::thread engine;
+
+    void run();
+    bool start(Request* r, std::string& err);
+    void finish(Request* r, int state, const std::string& err);
+};
+
+void awe_server_s::finish(Request* r, int state, const std::string& err) {
+    // caller does not hold mu
+    if (r->plan) awe_plan_destroy(r->plan);
+    r->plan = nullptr;
+    if (r->chunk_done) (void)hipEventDestroy(r->chunk_done);
+    if (r->stream) (void)hipStreamDestroy(r->stream);
+    for (float* p : {r->d_m, r->d_wav, r->d_tr})
+        if (p) (void)hipFree(p);
+    r->d_m = r->d_wav = r->d_tr = nullptr;
+    r->chunk_done = nullptr;
+    r->stream = nullptr;
+    std::vector<float>().swap(r->m);
+    std::vector<float>().swap(r->wavelet);
+    std::lock_guard<std::mutex> lk(mu);
+    r->state = state;
+    r->err = err;
+    r->t[3] = now_s(t0);
+    reserved -= r->bytes;
+    if (state == AWE_REQ_DONE) ++n_completed;
+    else ++n_failed;
+    changed.notify_all();
+}
+
+bool awe_server_s::start(Request* r, std::string& err) {
+    auto hip_ok = [&](hipError_t e, const char* what) {
+        if (e == hipSuccess) return true;
+        err = std::string(what) + ": " + hipGetErrorString(e);
+        return false;
+    };
+    awe_status st = awe_plan_create(&r->g, &r->plan);
+    if (st) { err = awe_last_error(); return false; }
+    if (!hip_ok(hipStreamCreateWithFlags(&r->stream, hipStreamNonBlocking), "hipStreamCreate")) return false;
+    if (!hip_ok(hipEventCreateWithFlags(&r->chunk_done, hipEventDisableTiming), "hipEventCreate")) return false;
+    const size_t nm = r->m.size(), nw = r->wavelet.size(), ntr = (size_t)r->g.nt * r->g.nrec;
+    if (!hip_ok(hipMalloc(&r->d_m, nm * sizeof(float)), "hipMalloc")) return false;
+    if (nw && !hip_ok(hipMalloc(&r->d_wav, nw * sizeof(float)), "hipMalloc")) return false;
+    if (ntr && !hip_ok(hipMalloc(&r->d_tr, ntr * sizeof(float)), "hipMalloc")) return false;
+    if (!hip_ok(hipMemcpyAsync(r->d_m, r->m.data(), nm * sizeof(float), hipMemcpyHostToDevice, r->stream), "copy m"))
+        return false;
+    if (nw && !hip_ok(hipMemcpyAsync(r->d_wav, r->wavelet.data(), nw * sizeof(float), hipMemcpyHostToDevice,
+                                     r->stream), "copy wavelet"))
+        return false;
+    st = awe_set_model(r->plan, r->d_m, r->stream);   // synchronises r->stream
+    if (st) { err = awe_last_error(); return false; }
+    if (ntr && !hip_ok(awe::launch_fill(r->d_tr, r->g.nrec, 0.f, r->stream), "zero traces")) return false;
+    // zero initial state, as in awe_forward
+    if (!hip_ok(awe::launch_fill(r->plan->w0, r->plan->L.total, 0.f, r->stream), "zero state")) return false;
+    if (!hip_ok(awe::launch_fill(r->plan->w1, r->plan->L.total, 0.f, r->stream), "zero state")) return false;
+    r->plan->cur = r->plan->w0;
+    r->plan->prev = r->plan->w1;
+    r->next = 0;
+    return true;
+}
+
+void awe_server_s::run() {
+    (void)hipSetDevice(device);
+    for (;;) {
+        std::vector<Request*> admitted;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            wake.wait(lk, [&] { return stop || !queue.empty() || !active.empty(); });
+            if (stop && active.empty()) break;
+            // FIFO admission: the head waits until it fits (no overtaking).
+            while (!stop && !queue.empty() && (int)active.size() + (int)admitted.size() < max_active &&
+                   reserved + queue.front()->bytes <= budget) {
+                Request* r = queue.front();
+                queue.pop_front();
+                reserved += r->bytes;
+                r->state = AWE_REQ_RUNNING;
+                r->t[1] = now_s(t0);
+                ++n_admitted;
+                admitted.push_back(r);
+            }
+        }
+        for (Request* r : admitted) {
+            std::string err;
+            if (start(r, err)) {
+                std::lock_guard<std::mutex> lk(mu);
+                r->t[2] = now_s(t0);
+                active.push_back(r);
+            } else {
+                finish(r, AWE_REQ_FAILED, err);
+            }
+        }
+        // one iteration: enqueue a chunk of every running request
+        std::vector<Request*> running;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            running = active;
+        }
+        for (Request* r : running) {
+            if (r->copying) continue;
+            const int last = r->g.nt - 1;
+            const int n = std::min(chunk, last - r->next);
+            if (n > 0) {
+                awe_status st = r->plan->step(r->next, n, r->d_wav, r->d_tr, r->stream);
+                if (st) {
+                    std::string err = awe_last_error();
+                    { std::lock_guard<std::mutex> lk(mu); active.erase(std::find(active.begin(), active.end(), r)); }
+                    finish(r, AWE_REQ_FAILED, err);
+                    continue;
+                }
+                r->next += n;
+            }
+            if (r->next >= last) {
+                const size_t ntr = (size_t)r->g.nt * r->g.nrec;
+                if (ntr) (void)hipMemcpyAsync(r->traces_host, r->d_tr, ntr * sizeof(float), hipMemcpyDeviceToHost,
+                                              r->stream);
+                r->copying = true;
+            }
+            (void)hipEventRecord(r->chunk_done, r->stream);
+        }
+        // wait for this iteration's chunks; retire finished requests
+        for (Request* r : running) {
+            if (!r->chunk_done) continue;
+            hipError_t e = hipEventSynchronize(r->chunk_done);
+            if (e != hipSuccess || r->copying) {
+                { std::lock_guard<std::mutex> lk(mu); active.erase(std::find(active.begin(), active.end(), r)); }
+                finish(r, e == hipSuccess ? AWE_REQ_DONE : AWE_REQ_FAILED,
+                       e == hipSuccess ? "" : hipGetErrorString(e));
+            }
+        }
+        std::lock_guard<std::mutex> lk(mu);
+        ++iterations;
+    }
+}
+
+extern "C" {
+
+awe_status awe_server_create(double hbm_fraction, int32_t chunk_steps, int32_t max_active, awe_server* out) {
+    if (!out) return fail(AWE_EINVAL, "output pointer is NULL");
+    *out = nullptr;
+    if (!(hbm_fraction > 0.0 && hbm_fraction <= 1.0)) return fail(AWE_EINVAL, "hbm_fraction must be in (0, 1]");
+    if (chunk_steps < 1 || max_active < 1) return fail(AWE_EINVAL, "chunk_steps and max_active must be >= 1");
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(AWE_ENODEV, "no HIP device available");
+    }
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return fail(AWE_EHIP, "hipMemGetInfo failed");
+    awe_server s = new (std::nothrow) awe_server_s();
+    if (!s) return fail(AWE_ENOMEM, "host allocation failed");
+    s->device = dev;
+    s->chunk = chunk_steps;
+    s->max_active = max_active;
+    s->budget = (uint64_t)(hbm_fraction * (double)free_b);
+    if (const char* env = std::getenv("AWE_SERVER_BUDGET_BYTES")) {
+        const unsigned long long b = std::strtoull(env, nullptr, 10);
+        if (b > 0) s->budget = std::min<uint64_t>(s->budget, b);
+    }
+    s->engine = std::thread([s] { s->run(); });
+    *out = s;
+    return AWE_OK;
+}
+
+awe_status awe_server_submit(awe_server srv, const awe_geometry* g, const float* m, const float* wavelet,
+                             float* traces, int64_t* ticket) {
+    if (!srv || !ticket) return fail(AWE_EINVAL, "NULL argument");
+    awe_status st = awe::validate(g);
+    if (st) return st;
+    if (!m) return fail(AWE_EINVAL, "model is NULL");
+    if (g->nsrc > 0 && !wavelet) return fail(AWE_EINVAL, "wavelet is NULL");
+    if (g->nrec > 0 && !traces) return fail(AWE_EINVAL, "traces is NULL");
+    auto r = std::make_unique<Request>();
+    r->g = *g;
+    r->src.assign(g->src_coords, g->src_coords + (size_t)g->nsrc * g->ndim);
+    r->rec.assign(g->rec_coords, g->rec_coords + (size_t)g->nrec * g->ndim);
+    r->g.src_coords = r->src.data();
+    r->g.rec_coords = r->rec.data();
+    size_t nm = 1;
+    for (int a = 0; a < g->ndim; ++a) nm *= (size_t)g->shape[a];
+    r->m.assign(m, m + nm);
+    if (g->nsrc > 0) r->wavelet.assign(wavelet, wavelet + (size_t)g->nt * g->nsrc);
+    r->traces_host = traces;
+    r->bytes = awe::footprint_bytes(g, 0) + nm * 4 + r->wavelet.size() * 4 + (size_t)g->nt * g->nrec * 4;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (srv->stop) return fail(AWE_EBUSY, "server is shutting down");
+    if (r->bytes > srv->budget)
+        return fail(AWE_ENOMEM, "request needs %llu bytes, budget is %llu", (unsigned long long)r->bytes,
+                    (unsigned long long)srv->budget);
+    r->id = srv->next_id++;
+    r->t[0] = now_s(srv->t0);
+    *ticket = r->id;
+    srv->queue.push_back(r.get());
+    srv->all[r->id] = std::move(r);
+    ++srv->n_submitted;
+    srv->wake.notify_all();
+    return AWE_OK;
+}
+
+awe_status awe_server_poll(awe_server srv, int64_t ticket, int32_t* state, double* times) {
+    if (!srv || !state) return fail(AWE_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    auto it = srv->all.find(ticket);
+    if (it == srv->all.end()) return fail(AWE_EINVAL, "unknown ticket %lld", (long long)ticket);
+    Request* r = it->second.get();
+    *state = r->state;
+    if (times)
+        for (int i = 0; i < 4; ++i) times[i] = r->t[i];
+    if (r->state == AWE_REQ_FAILED) awe::t_err = r->err;
+    return AWE_OK;
+}
+
+awe_status awe_server_wait(awe_server srv, int64_t ticket, double timeout_s) {
+    if (!srv) return fail(AWE_EINVAL, "NULL argument");
+    std::unique_lock<std::mutex> lk(srv->mu);
+    auto it = srv->all.find(ticket);
+    if (it == srv->all.end()) return fail(AWE_EINVAL, "unknown ticket %lld", (long long)ticket);
+    Request* r = it->second.get();
+    auto done = [&] { return r->state == AWE_REQ_DONE || r->state == AWE_REQ_FAILED; };
+    if (!srv->changed.wait_for(lk, std::chrono::duration<double>(timeout_s), done))
+        return fail(AWE_EBUSY, "request %lld still running", (long long)ticket);
+    if (r->state == AWE_REQ_FAILED) return fail(AWE_EINVAL, "request failed: %s", r->err.c_str());
+    return AWE_OK;
+}
+
+awe_status awe_server_stats(awe_server srv, int64_t* out) {
+    if (!srv || !out) return fail(AWE_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    out[0] = srv->n_submitted;
+    out[1] = srv->n_admitted;
+    out[2] = srv->n_completed;
+    out[3] = srv->n_failed;
+    out[4] = (int64_t)srv->active.size();
+    out[5] = (int64_t)srv->queue.size();
+    out[6] = (int64_t)srv->reserved;
+    out[7] = srv->iterations;
+    return AWE_OK;
+}
+
+awe_status awe_server_destroy(awe_server srv) {
+    if (!srv) return AWE_OK;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stop = true;
+        for (Request* r : srv->queue) {
+            r->state = AWE_REQ_FAILED;
+            r->err = "server destroyed before the request was admitted";
+            ++srv->n_failed;
+        }
+        srv->queue.clear();
+        srv->wake.notify_all();
+        srv->changed.notify_all();
+    }
+    if (srv->engine.joinable()) srv->engine.join();
+    delete srv;
+    return AWE_OK;
+}
+
+}  // extern "C"
