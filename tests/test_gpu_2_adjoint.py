@@ -38,35 +38,95 @@ def test_dot_product(kind, order):
     assert np.all(fty[-1] == 0.0)
 
 
-def _gradient_case(shot, K, seed=0):
+def _gradient_case(shot, K, seed=0, amp=0.05):
     dt = shot_dt(shot)
     rng = np.random.default_rng(seed)
-    w = shot.wavelet(dt)
-    m_true = shot.m * (1.0 + 0.05 * synth.random_state(rng, shot.shape, 2.0))
+    w = shot.wavelet(dt).astype(np.float32)
+    m_true = shot.m * (1.0 + amp * synth.random_state(rng, shot.shape, 2.0))
     op_true = oracle.Operator(oracle_problem(shot, dt), m_true)
     d_obs = op_true.forward(w)["traces"].astype(np.float32)
     return dt, w, d_obs
 
 
-@pytest.mark.parametrize("kind,order,K", [("2d", 4, 25), ("2d", 16, 7), ("3d", 8, 10), ("3d", 4, 33)])
-def test_gradient_matches_oracle(kind, order, K):
-    shot = small_2d_shot(500 + order, order, nt=200) if kind == "2d" else small_3d_shot(500 + order, order, nt=90)
-    dt, w, d_obs = _gradient_case(shot, K)
-    log(f"case {shot.name} K={K}")
-    ref = oracle.Operator(oracle_problem(shot, dt), shot.m).gradient(w.astype(np.float32), d_obs)
+def _gpu_gradient(shot, dt, w, K, resid=None, d_obs=None):
+    """GPU forward with checkpoints, then the adjoint-state gradient driven by
+    `resid` (given) or by traces - d_obs (computed on the device)."""
+    import paper_1608_08658_amd as awe
     plan = gpu_plan(shot, dt)
     plan.set_model(dev(shot.m))
-    import paper_1608_08658_amd as awe
     tr = plan.forward(dev(w), ckpt_every=K)
-    phi, resid = awe.misfit(tr, dev(d_obs))
-    _, g = plan.adjoint(resid, want_src_adj=False, want_grad=True)
-    g = host(g)
-    gp = host(plan.gradient_padded())
+    phi = None
+    if resid is None:
+        phi, r = awe.misfit(tr, dev(d_obs))
+    else:
+        r = dev(resid)
+    _, g = plan.adjoint(r, want_src_adj=False, want_grad=True)
+    out = host(g), host(plan.gradient_padded()), phi, host(tr)
     plan.close()
-    e_g, e_gp = rel_l2(g, ref["grad"]), rel_l2(gp, ref["grad_pad"])
-    log(f"  phi gpu {phi:.6e} oracle {ref['phi']:.6e}; grad rel {e_g:.2e} padded {e_gp:.2e}")
-    assert phi == pytest.approx(ref["phi"], rel=1e-4)
+    return out
+
+
+@pytest.mark.parametrize("kind,order,K", [("2d", 4, 25), ("2d", 16, 7), ("3d", 8, 10), ("3d", 4, 33),
+                                          ("3d", 16, 1)])
+def test_gradient_operator_matches_oracle(kind, order, K):
+    # J^T applied to one and the same residual on both sides (the residual is
+    # the oracle's, rounded to FP32): the adjoint-state gradient of Eq. (3).
+    shot = small_2d_shot(500 + order, order, nt=200) if kind == "2d" else small_3d_shot(500 + order, order, nt=90)
+    dt, w, d_obs = _gradient_case(shot, K)
+    op = oracle.Operator(oracle_problem(shot, dt), shot.m)
+    fwd = op.forward(w, keep=True)
+    resid = (fwd["traces"] - d_obs).astype(np.float32)
+    adj = op.adjoint(resid, history=fwd["history"])
+    g_ref_pad = adj["grad_pad"]
+    g_ref = oracle.fold_padding(g_ref_pad, shot.nbl)
+    g, gp, _, _ = _gpu_gradient(shot, dt, w, K, resid=resid)
+    e_g, e_gp = rel_l2(g, g_ref), rel_l2(gp, g_ref_pad)
+    log(f"case {shot.name} K={K}: grad rel {e_g:.2e}, padded {e_gp:.2e}")
     assert e_g <= 1e-4 and e_gp <= 1e-4
+
+
+@pytest.mark.parametrize("kind,order,amp", [("2d", 4, 0.05), ("3d", 8, 0.10)])
+def test_gradient_end_to_end(kind, order, amp):
+    # Inputs m, wavelet, d_obs -> misfit and gradient.  The residual is a
+    # difference of nearby traces, so an FP32 trace error eps is amplified by
+    # kappa = |d| / |d - d_obs|; the bound is the operator tolerance plus
+    # eps * kappa with eps = 1e-5 (the forward's FP32 error level, a tenth of
+    # the trace tolerance), and 2 eps kappa for the misfit.
+    shot = small_2d_shot(510 + order, order, nt=200) if kind == "2d" else small_3d_shot(510 + order, order, nt=90)
+    dt, w, d_obs = _gradient_case(shot, 10, amp=amp)
+    ref = oracle.Operator(oracle_problem(shot, dt), shot.m).gradient(w, d_obs)
+    kappa = np.linalg.norm(ref["traces"]) / np.linalg.norm(ref["traces"] - d_obs)
+    g, gp, phi, tr = _gpu_gradient(shot, dt, w, 10, d_obs=d_obs)
+    e_g = rel_l2(g, ref["grad"])
+    e_phi = abs(phi - ref["phi"]) / ref["phi"]
+    log(f"case {shot.name}: kappa {kappa:.1f}, traces {rel_l2(tr, ref['traces']):.2e}, "
+        f"phi rel {e_phi:.2e}, grad rel {e_g:.2e}")
+    assert rel_l2(tr, ref["traces"]) <= 1e-4
+    assert e_phi <= 2e-5 * kappa
+    assert e_g <= 1e-4 + 1e-5 * kappa
+
+
+def test_autograd_matches_plan_calls():
+    import torch
+    import paper_1608_08658_amd as awe
+    shot = small_2d_shot(520, 8, nt=150)
+    dt, w, d_obs = _gradient_case(shot, 10)
+    plan = gpu_plan(shot, dt)
+    m = torch.tensor(shot.m, dtype=torch.float32, device="cuda", requires_grad=True)
+    wt = torch.tensor(w, device="cuda", requires_grad=True)
+    tr = awe.Gradient.apply(m, wt, plan, 15)
+    loss = 0.5 * ((tr - dev(d_obs)) ** 2).sum()
+    loss.backward()
+    g_auto, gw_auto = host(m.grad), host(wt.grad)
+    # the same through the plan
+    plan.set_model(dev(shot.m))
+    tr2 = plan.forward(dev(w), ckpt_every=15)
+    resid = tr2 - dev(d_obs)
+    src_adj, g = plan.adjoint(resid.contiguous(), want_src_adj=True, want_grad=True)
+    assert np.array_equal(host(tr.detach()), host(tr2))
+    assert np.array_equal(g_auto, host(g))
+    assert np.array_equal(gw_auto, host(src_adj))
+    plan.close()
 
 
 def test_gradient_is_independent_of_checkpoint_interval():
@@ -148,6 +208,8 @@ def test_misfit_matches_numpy():
     a = rng.standard_normal((777, 33)).astype(np.float32)
     b = rng.standard_normal((777, 33)).astype(np.float32)
     phi, r = awe.misfit(dev(a), dev(b))
-    ref = 0.5 * np.sum((a.astype(np.float64) - b) ** 2)
+    # the residual is formed in FP32 (as stored), its square summed in FP64
+    r32 = (a - b).astype(np.float64)
+    ref = 0.5 * np.sum(r32 * r32)
     assert phi == pytest.approx(ref, rel=1e-12)
     assert np.array_equal(host(r), (a - b).astype(np.float64))
