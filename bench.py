@@ -62,6 +62,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=4, help="oracle time steps for the CPU baseline (0 = skip)")
     ap.add_argument("--n", type=int, default=256, help="physical grid points per axis")
     ap.add_argument("--nt", type=int, default=1000)
+    ap.add_argument("--copy-ref-mb", type=int, default=0,
+                    help="also run a plain device-to-device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (shots would shard one per GPU, "
@@ -121,6 +123,18 @@ def main():
     log(f"stencil kernel: {kern_s * 1e6:.1f} us/launch, {achieved:.0f} GB/s algorithmic "
         f"({100 * achieved / HBM_PEAK_GBS:.1f}% of {HBM_PEAK_GBS:.0f} GB/s)")
     plan.close()
+
+    if args.copy_ref_mb > 0:
+        # a plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE per
+        # dispatch calibrate the counters against bytes actually moved
+        nel = args.copy_ref_mb * (1 << 20) // 4
+        src = torch.ones(nel, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"reference copy: {args.copy_ref_mb} MiB read + written, 3 times")
+        del src, dst
 
     base = None
     if args.cpu_steps > 0:

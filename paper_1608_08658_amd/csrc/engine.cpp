@@ -10,7 +10,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <set>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -314,22 +316,7 @@ awe_status Plan::init(const awe_geometry* geo) {
     }
     k.inv_dt = (float)(1.0 / g.dt);
 
-    // launch shape: AWE_TILE="cfg,zchunk" overrides the default
-    tile_cfg = 0;
-    if (g.ndim == 3) {
-        const int64_t tiles = ((pad[2] + kTileX - 1) / kTileX) * ((pad[1] + tile_rows(3, 0) - 1) / tile_rows(3, 0));
-        const int64_t want = std::max<int64_t>(1, (2048 + tiles - 1) / tiles);
-        zchunk = (int)std::max<int64_t>(16, (pad[0] + want - 1) / want);
-    } else {
-        zchunk = 32;
-    }
-    if (const char* env = std::getenv("AWE_TILE")) {
-        int cfg = -1, zc = -1;
-        if (std::sscanf(env, "%d,%d", &cfg, &zc) == 2 && cfg >= 0 && cfg < num_tile_cfgs(g.ndim) && zc > 0) {
-            tile_cfg = cfg;
-            zchunk = zc;
-        }
-    }
+    fwd_shape = img_shape = default_shape(L);
 
     // damping tables
     std::vector<double> ez, ey, ex;
@@ -373,6 +360,97 @@ awe_status Plan::init(const awe_geometry* geo) {
     AWE_HIP(hipDeviceSynchronize());
     cur = w0;
     prev = w1;
+    return tune(false, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// Launch-shape autotuning (the GPU counterpart of the paper's block-size
+// autotuning, Sec. IV.B.3): time each candidate workgroup shape and z-chunk
+// length on this plan's own buffers and keep the fastest.  Every shape
+// computes the same arithmetic per point, so the choice never changes results.
+// Results are cached per (device, dimensions, order, padded grid, kernel).
+// AWE_TILE="cfg,zchunk" forces a shape; AWE_AUTOTUNE=0 keeps the default.
+// ---------------------------------------------------------------------------
+namespace {
+struct TuneKey {
+    int dev, ndim, half, img;
+    int64_t n0, n1, n2;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(dev, ndim, half, img, n0, n1, n2) < std::tie(o.dev, o.ndim, o.half, o.img, o.n0, o.n1, o.n2);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, LaunchShape> g_tune_cache;
+constexpr int64_t kTuneMinPoints = 4 << 20;
+}  // namespace
+
+LaunchShape awe::default_shape(const Layout& L) {
+    return L.ndim == 3 ? LaunchShape{3, 56} : LaunchShape{0, 32};
+}
+
+awe_status Plan::tune(bool img, hipStream_t user_stream) {
+    LaunchShape& shape = img ? img_shape : fwd_shape;
+    if (const char* env = std::getenv("AWE_TILE")) {
+        int cfg = -1, zc = -1;
+        if (std::sscanf(env, "%d,%d", &cfg, &zc) == 2 && cfg >= 0 && cfg < num_tile_cfgs(g.ndim) && zc > 0) {
+            shape = {cfg, zc};
+            return AWE_OK;
+        }
+    }
+    const char* off = std::getenv("AWE_AUTOTUNE");
+    if ((off && off[0] == '0') || L.points() < kTuneMinPoints) return AWE_OK;
+    const TuneKey key{device, g.ndim, half, img ? 1 : 0, L.n[0], L.n[1], L.n[2]};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            shape = it->second;
+            return AWE_OK;
+        }
+    }
+    std::vector<LaunchShape> cand;
+    if (g.ndim == 3) {
+        for (int cfg : {0, 1, 3})
+            for (int zc : {28, 42, 56, 70, 84}) cand.push_back({cfg, zc});
+    } else {
+        for (int zc : {16, 32, 64, 128}) cand.push_back({0, zc});
+        for (int zc : {32, 64, 128}) cand.push_back({1, zc});
+    }
+    hipStream_t s = user_stream;
+    bool own = false;
+    if (!s) {
+        AWE_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        own = true;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    awe_status st = AWE_OK;
+    float best_ms = 1e30f;
+    LaunchShape best = shape;
+    StepArgs a = img ? StepArgs{mu0, mu1, mu1, coef, d_ez, d_ey, d_ex, w0, grad}
+                     : StepArgs{w0, w1, w1, coef, d_ez, d_ey, d_ex, nullptr, nullptr};
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    for (size_t i = 0; e == hipSuccess && i < cand.size(); ++i) {
+        for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch_step(L, k, a, img, cand[i].cfg, cand[i].zchunk, s);
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        for (int w = 0; w < 6 && e == hipSuccess; ++w) e = launch_step(L, k, a, img, cand[i].cfg, cand[i].zchunk, s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && ms < best_ms) {
+            best_ms = ms;
+            best = cand[i];
+        }
+    }
+    if (e != hipSuccess) st = fail(AWE_EHIP, "autotune: %s", hipGetErrorString(e));
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (own) (void)hipStreamDestroy(s);
+    if (st) return st;
+    shape = best;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = best;
     return AWE_OK;
 }
 
@@ -405,7 +483,7 @@ awe_status Plan::set_model(const float* m, hipStream_t s) {
 // One step of the recurrence from (uc, up) into out, then the point source.
 awe_status Plan::advance(const float* uc, const float* up, float* out, const float* q_row, hipStream_t s) {
     StepArgs a{uc, up, out, coef, d_ez, d_ey, d_ex, nullptr, nullptr};
-    AWE_HIP(launch_step(L, k, a, false, tile_cfg, zchunk, s));
+    AWE_HIP(launch_step(L, k, a, false, fwd_shape.cfg, fwd_shape.zchunk, s));
     if (q_row && g.nsrc > 0)
         AWE_HIP(launch_inject(out, coef, src_csr.node, src_csr.rowptr, src_csr.pt, src_csr.w, src_csr.nrows, q_row,
                               (float)(1.0 / vol), nullptr, nullptr, s));
@@ -504,6 +582,10 @@ awe_status Plan::adjoint(const float* resid, float* src_adj, float* grad_phys, h
     awe_status st;
     if (!mu0 && ((st = alloc_field(&mu0)) || (st = alloc_field(&mu1)))) return st;
     if (want_grad && !grad && (st = alloc_field(&grad))) return st;
+    if (want_grad && !img_tuned) {
+        if ((st = tune(true, s))) return st;
+        img_tuned = true;
+    }
     AWE_HIP(launch_fill(mu0, L.total, 0.f, s));
     AWE_HIP(launch_fill(mu1, L.total, 0.f, s));
     if (want_grad) AWE_HIP(launch_fill(grad, L.total, 0.f, s));
@@ -517,7 +599,8 @@ awe_status Plan::adjoint(const float* resid, float* src_adj, float* grad_phys, h
             AWE_HIP(launch_sample(src_adj + (size_t)n * g.nsrc, m1, src_node, src_w, g.nsrc, corners, inv_vol, s));
         const bool img = usnap != nullptr;
         StepArgs a{m1, m2, m2, coef, d_ez, d_ey, d_ex, usnap, img ? grad : nullptr};
-        AWE_HIP(launch_step(L, k, a, img, tile_cfg, zchunk, s));
+        const LaunchShape& sh = img ? img_shape : fwd_shape;
+        AWE_HIP(launch_step(L, k, a, img, sh.cfg, sh.zchunk, s));
         if (g.nrec > 0)
             AWE_HIP(launch_inject(m2, coef, rec_csr.node, rec_csr.rowptr, rec_csr.pt, rec_csr.w, rec_csr.nrows,
                                   resid + (size_t)n * g.nrec, 1.f, usnap, img ? grad : nullptr, s));

@@ -25,6 +25,12 @@ std::vector<int> stored_times(int nt, int K);
 int segment_slots(int nt, int K);
 uint64_t footprint_bytes(const awe_geometry* g, int K);
 
+struct LaunchShape {
+    int cfg;        // workgroup shape (see launch_step)
+    int zchunk;     // z planes per workgroup
+};
+LaunchShape default_shape(const Layout& L);
+
 struct DeviceCsr {
     int64_t* node = nullptr;
     int32_t* rowptr = nullptr;
@@ -44,7 +50,8 @@ struct awe_plan_s {
     double vol = 1.0;
     awe::Layout L;
     awe::StencilCoef k{};
-    int tile_cfg = 0, zchunk = 32;
+    awe::LaunchShape fwd_shape{3, 56}, img_shape{3, 56};   // stencil launch shapes (forward / imaging)
+    bool img_tuned = false;
 
     // device buffers owned by the plan
     std::vector<void*> owned;
@@ -89,6 +96,7 @@ struct awe_plan_s {
     void release(void* p);
     awe_status advance(const float* uc, const float* up, float* out, const float* q_row, hipStream_t s);
     awe_status ensure_gradient_storage(int K);
+    awe_status tune(bool img, hipStream_t user_stream);
     float* pick_work_dst();
 };
 

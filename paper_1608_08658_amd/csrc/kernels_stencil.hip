@@ -29,6 +29,12 @@
 namespace awe {
 namespace {
 
+// s_waitcnt vmcnt(0) (gfx9 encoding: expcnt and lgkmcnt left at their maxima).
+// Used once after the queue is filled: with no load of the prologue still in
+// flight when the loop starts, the compiler's wait analysis does not carry
+// them into the loop, where they would force a full drain on every plane.
+__device__ __forceinline__ void drain_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 __device__ __forceinline__ void lds_barrier() {
     // Orders the LDS writes of this plane before other waves read them.  Only
     // LDS needs to be visible across the workgroup; outstanding global loads
@@ -41,7 +47,49 @@ __device__ __forceinline__ void lds_barrier() {
 struct Geo3 {
     int32_t nz, ny, nx;
     int64_t sy, sz, origin;
+    uint32_t gx, gy, ntiles;     // tile grid (x tiles, y tiles) and total tiles incl. z chunks
+    int64_t total;               // elements in each field's allocation
 };
+
+// Workgroups are dealt to the 8 XCDs round-robin by linear id, and each XCD
+// has its own L2.  Remap so that XCD k runs the contiguous logical range
+// [k*per, (k+1)*per) of tiles (x fastest, then y, then z chunk): tiles that
+// share halo rows and columns then run at the same time on the same L2.
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ bool xcd_tile(const Geo3& g, uint32_t& bx, uint32_t& by, uint32_t& bz) {
+    const uint32_t per = gridDim.x / kXcds;
+    const uint32_t lin = (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+    if (lin >= g.ntiles) return false;
+    bx = lin % g.gx;
+    by = (lin / g.gx) % g.gy;
+    bz = lin / (g.gx * g.gy);
+    return true;
+}
+
+// Raw buffer access.  A descriptor covers one workgroup's slab of a field;
+// an offset at or beyond its size reads 0 and drops a store, so lanes with
+// nothing to load or store are given kOob instead of a branch.  The z-plane
+// offset is wave-uniform and goes in the scalar offset.
+constexpr uint32_t kOob = 0xFFFFFFF0u;
+constexpr int kRsrcWord3 = 0x00020000;   // gfx9 family: 32-bit data format
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t slab_rsrc(const float* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), 0, (int)bytes, kRsrcWord3);
+}
+// Cache policy of the arrays that are touched once per step (u[n-1], C, the
+// output, and with imaging the snapshot and gradient): the wavefield planes
+// re-read as halos and z-queue warm-up keep the default policy.
+#ifndef AWE_CPOL_STREAM
+#define AWE_CPOL_STREAM 2   // NT: stream through L2 with early eviction
+#endif
+template <int CPOL = 0>
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, CPOL));
+}
+template <int CPOL = 0>
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, float v, uint32_t voff, uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, CPOL);
+}
 
 template <int M, int BY, int RY, bool IMG>
 __global__ void __launch_bounds__(kTileX * BY)
@@ -53,52 +101,62 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk) {
     constexpr int NH = (2 * M + BY - 1) / BY;     // y-halo rows per thread row
     __shared__ float lds[2][LH][LW];
 
+    uint32_t bx, by, bz;
+    if (!xcd_tile(g, bx, by, bz)) return;          // uniform over the workgroup
     const int tx = threadIdx.x;
     const int ty = threadIdx.y;
-    const int x = blockIdx.x * kTileX + tx;
-    const int yb = blockIdx.y * TY;
+    const int x = bx * kTileX + tx;
+    const int yb = by * TY;
     const int y0 = yb + ty * RY;
-    const int z0 = blockIdx.z * zchunk;
+    const int z0 = bz * zchunk;
     const int z1 = min(z0 + zchunk, g.nz);
-    if (z0 >= z1) return;                          // uniform over the workgroup
+    if (z0 >= z1) return;
 
+    // slab base: grid point (z0 - M, -M, -M); every access of this workgroup
+    // lies at a non-negative offset from it and inside the allocation
     const int64_t sy = g.sy, sz = g.sz;
+    const int64_t slab = g.origin + (int64_t)(z0 - M) * sz - (int64_t)M * sy - M;
+    const uint64_t left = (uint64_t)(g.total - slab) * 4u;
+    const uint32_t bytes = left > 0x7FFFFFF0ull ? 0x7FFFFFF0u : (uint32_t)left;
+    const auto r_uc = slab_rsrc(a.uc + slab, bytes);
+    const auto r_up = slab_rsrc(a.up + slab, bytes);
+    const auto r_out = slab_rsrc(a.out + slab, bytes);
+    const auto r_cf = slab_rsrc(a.coef + slab, bytes);
+    const auto r_us = slab_rsrc(IMG ? a.usnap + slab : a.uc + slab, bytes);
+    const auto r_gr = slab_rsrc(IMG ? a.grad + slab : a.out + slab, bytes);
+    const uint32_t plane = (uint32_t)(sz * 4);     // bytes per z plane
+    auto soff = [&](int z) { return (uint32_t)(z - z0 + M) * plane; };
+    auto voff = [&](int y, int xx) { return (uint32_t)(((int64_t)(y + M) * sy + xx + M) * 4); };
+
     const bool xin = x < g.nx;                     // this lane owns a grid point
     const bool xld = x < g.nx + M;                 // this lane's column is in the allocation
-    bool rin[RY], rld[RY];
+    uint32_t o_in[RY], o_ld[RY];                   // per-row offsets for owned / loadable points
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
-        rin[r] = xin && (y0 + r < g.ny);
-        rld[r] = xld && (y0 + r < g.ny + M);
+        const uint32_t o = voff(y0 + r, x);
+        o_in[r] = (xin && y0 + r < g.ny) ? o : kOob;
+        o_ld[r] = (xld && y0 + r < g.ny + M) ? o : kOob;
     }
     // x halo: lanes tx < M load the left columns, lanes tx >= 64-M the right ones.
     const bool hl = tx < M;
     const bool hr = tx >= kTileX - M;
-    const int hx = hl ? (blockIdx.x * kTileX - M + tx) : (blockIdx.x * kTileX + M + tx);
+    const int hx = hl ? ((int)bx * kTileX - M + tx) : ((int)bx * kTileX + M + tx);
     const int hlx = hl ? tx : (tx + 2 * M);        // LDS column of the halo value
-    const bool hxl = (hl || hr) && (hx < g.nx + M);
+    uint32_t o_hx[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r)
+        o_hx[r] = ((hl || hr) && hx < g.nx + M && y0 + r < g.ny + M) ? voff(y0 + r, hx) : kOob;
     // y halo: 2M rows (M above, M below the tile), 64 columns; thread row ty
     // loads halo rows h = ty, ty + BY, ... < 2M.
-    int hyrow[NH];                                 // LDS row of each halo value
-    bool hyl[NH];                                  // load it (valid and in the allocation)
-    int64_t hyoff[NH];                             // its offset from the thread's row y0
+    int hyrow[NH];
+    uint32_t o_hy[NH];
 #pragma unroll
     for (int i = 0; i < NH; ++i) {
         const int h = ty + i * BY;
         const int y = (h < M) ? (yb - M + h) : (yb + TY + (h - M));
         hyrow[i] = (h < M) ? h : (TY + h);
-        hyl[i] = (h < 2 * M) && xld && (y < g.ny + M);
-        hyoff[i] = (int64_t)(y - y0) * sy;
+        o_hy[i] = ((h < 2 * M) && xld && (y < g.ny + M)) ? voff(y, x) : kOob;
     }
-
-    const int64_t base = g.origin + (int64_t)y0 * sy + x;   // (z = 0, row y0, column x)
-    const float* uc = a.uc + base;
-    const float* up = a.up + base;
-    float* out = a.out + base;
-    const float* cf = a.coef + base;
-    const float* us = IMG ? a.usnap + base : nullptr;
-    float* gr = IMG ? a.grad + base : nullptr;
-    const float* uch = a.uc + g.origin + (int64_t)y0 * sy + hx;   // x-halo column
 
     const float exv = xin ? a.eta_x[x] : 0.f;
     float eyv[RY];
@@ -108,30 +166,30 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk) {
     // register queue of the z-neighbourhood: q[r][j] = uc(z - M + j)
     float q[RY][NQ];
 #pragma unroll
-    for (int j = 1; j < NQ; ++j) {
-        const int64_t zo = (int64_t)(z0 - M + j - 1) * sz;
+    for (int j = 1; j < NQ; ++j)
 #pragma unroll
-        for (int r = 0; r < RY; ++r) q[r][j] = rld[r] ? uc[zo + r * sy] : 0.f;
-    }
+        for (int r = 0; r < RY; ++r) q[r][j] = bload(r_uc, o_ld[r], soff(z0 - M + j - 1));
+    drain_vmem();
 
-    // prefetch registers for plane z
-    float fr[RY], pv[RY], cv[RY], sv[RY], gv[RY], hxv[RY], hyv[NH];
+    float fr[RY], pv[RY], cv[RY], sv[RY], gv[RY], hxv[RY], hyv[NH], ezn;
     auto fetch = [&](int z) {
-        const int64_t zo = (int64_t)z * sz;
-        const int64_t zf = (int64_t)(z + M) * sz;
+        // first in the batch: vector-memory counters retire in order, so the
+        // compute of plane z - 1 only waits for loads issued before this one
+        ezn = a.eta_z[z];
+        const uint32_t so = soff(z), sf = soff(z + M);
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-            fr[r] = rld[r] ? uc[zf + r * sy] : 0.f;
-            pv[r] = rin[r] ? up[zo + r * sy] : 0.f;
-            cv[r] = rin[r] ? cf[zo + r * sy] : 0.f;
+            fr[r] = bload(r_uc, o_ld[r], sf);
+            pv[r] = bload<AWE_CPOL_STREAM>(r_up, o_in[r], so);
+            cv[r] = bload<AWE_CPOL_STREAM>(r_cf, o_in[r], so);
             if (IMG) {
-                sv[r] = rin[r] ? us[zo + r * sy] : 0.f;
-                gv[r] = rin[r] ? gr[zo + r * sy] : 0.f;
+                sv[r] = bload<AWE_CPOL_STREAM>(r_us, o_in[r], so);
+                gv[r] = bload<AWE_CPOL_STREAM>(r_gr, o_in[r], so);
             }
-            hxv[r] = (hxl && (y0 + r < g.ny + M)) ? uch[zo + r * sy] : 0.f;
+            hxv[r] = bload(r_uc, o_hx[r], so);
         }
 #pragma unroll
-        for (int i = 0; i < NH; ++i) hyv[i] = hyl[i] ? uc[zo + hyoff[i]] : 0.f;
+        for (int i = 0; i < NH; ++i) hyv[i] = bload(r_uc, o_hy[i], so);
     };
     fetch(z0);
 
@@ -160,11 +218,11 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk) {
             c[r] = cv[r];
             if (IMG) { s[r] = sv[r]; gg[r] = gv[r]; }
         }
+        const float ezv = ezn;
         if (z + 1 < z1) fetch(z + 1);
         lds_barrier();
 
-        const float ezv = a.eta_z[z];
-        const int64_t zo = (int64_t)z * sz;
+        const uint32_t so = soff(z);
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             const int ly = M + ty * RY + r;
@@ -181,20 +239,18 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk) {
             const float u0 = q[r][M];
             const float av = (ezv + eyv[r] + exv) * c[r] * k.inv_dt;
             const float t = c[r] * lap + av * (p[r] - u0);
-            if (rin[r]) {
-                out[zo + r * sy] = (u0 - p[r]) + u0 + t;
-                if (IMG) gr[zo + r * sy] = gg[r] + s[r] * t;
-            }
+            bstore<AWE_CPOL_STREAM>(r_out, (u0 - p[r]) + u0 + t, o_in[r], so);
+            if (IMG) bstore<AWE_CPOL_STREAM>(r_gr, gg[r] + s[r] * t, o_in[r], so);
         }
     }
 }
 
 struct Geo2 {
     int32_t nz, nx;
-    int64_t sz, origin;
+    int64_t sz, origin, total;
 };
 
-// 2-D: block = 64 x NW threads; wave w streams z planes [z0 + w*zchunk, ...).
+// 2-D: block = 64 x NW threads; wave w streams z planes [zw, zw + zchunk).
 template <int M, int NW, bool IMG>
 __global__ void __launch_bounds__(kTileX * NW)
 step2d(StepArgs a, StencilCoef k, Geo2 g, int zchunk) {
@@ -206,46 +262,51 @@ step2d(StepArgs a, StencilCoef k, Geo2 g, int zchunk) {
     const int w = threadIdx.y;
     const int x = blockIdx.x * kTileX + tx;
     const int zw = (blockIdx.y * NW + w) * zchunk;        // first plane of this wave
-    const int zend = min(zw + zchunk, g.nz);              // may be <= zw for idle waves
+    const int zend = min(zw + zchunk, g.nz);              // <= zw for an idle wave
+    const bool live_wave = zw < g.nz;
+
+    // slab base: grid point (zw - M, -M); an idle wave gets an empty slab
     const int64_t sz = g.sz;
+    const int64_t slab = live_wave ? g.origin + (int64_t)(zw - M) * sz - M : 0;
+    const uint64_t left = live_wave ? (uint64_t)(g.total - slab) * 4u : 0;
+    const uint32_t bytes = left > 0x7FFFFFF0ull ? 0x7FFFFFF0u : (uint32_t)left;
+    const auto r_uc = slab_rsrc(a.uc + slab, bytes);
+    const auto r_up = slab_rsrc(a.up + slab, bytes);
+    const auto r_out = slab_rsrc(a.out + slab, bytes);
+    const auto r_cf = slab_rsrc(a.coef + slab, bytes);
+    const auto r_us = slab_rsrc(IMG ? a.usnap + slab : a.uc + slab, bytes);
+    const auto r_gr = slab_rsrc(IMG ? a.grad + slab : a.out + slab, bytes);
+    const uint32_t plane = (uint32_t)(sz * 4);
+    auto soff = [&](int z) { return (uint32_t)(z - zw + M) * plane; };
+
     const bool xin = x < g.nx;
     const bool xld = x < g.nx + M;
+    const uint32_t o_in = xin ? (uint32_t)(x + M) * 4u : kOob;
+    const uint32_t o_ld = xld ? (uint32_t)(x + M) * 4u : kOob;
     const bool hl = tx < M;
     const bool hr = tx >= kTileX - M;
-    const int hx = hl ? (blockIdx.x * kTileX - M + tx) : (blockIdx.x * kTileX + M + tx);
+    const int hx = hl ? ((int)blockIdx.x * kTileX - M + tx) : ((int)blockIdx.x * kTileX + M + tx);
     const int hlx = hl ? tx : (tx + 2 * M);
-    const bool hxl = (hl || hr) && (hx < g.nx + M);
-
-    const int64_t base = g.origin + x;
-    const float* uc = a.uc + base;
-    const float* up = a.up + base;
-    float* out = a.out + base;
-    const float* cf = a.coef + base;
-    const float* us = IMG ? a.usnap + base : nullptr;
-    float* gr = IMG ? a.grad + base : nullptr;
-    const float* uch = a.uc + g.origin + hx;
+    const uint32_t o_hx = ((hl || hr) && hx < g.nx + M) ? (uint32_t)(hx + M) * 4u : kOob;
     const float exv = xin ? a.eta_x[x] : 0.f;
 
-    // planes z in [-M, nz + M) are in the allocation
-    auto inz = [&](int z) { return z >= -M && z < g.nz + M; };
     float q[NQ];
 #pragma unroll
-    for (int j = 1; j < NQ; ++j) {
-        const int z = zw - M + j - 1;
-        q[j] = (xld && inz(z) && zw < g.nz) ? uc[(int64_t)z * sz] : 0.f;
-    }
-    float fr, pv, cv, sv = 0.f, gv = 0.f, hv;
+    for (int j = 1; j < NQ; ++j) q[j] = bload(r_uc, o_ld, soff(zw - M + j - 1));
+    drain_vmem();
+    float fr, pv, cv, sv = 0.f, gv = 0.f, hv, ezn;
     auto fetch = [&](int z) {
-        const bool live = z < zend;
-        const int64_t zo = (int64_t)z * sz;
-        fr = (live && xld) ? uc[zo + (int64_t)M * sz] : 0.f;
-        pv = (live && xin) ? up[zo] : 0.f;
-        cv = (live && xin) ? cf[zo] : 0.f;
+        const bool live = z < zend;                   // wave-uniform
+        ezn = live ? a.eta_z[z] : 0.f;                // first in the batch (in-order counters)
+        const uint32_t so = soff(z);
+        fr = bload(r_uc, live ? o_ld : kOob, soff(z + M));
+        pv = bload<AWE_CPOL_STREAM>(r_up, live ? o_in : kOob, so);
+        cv = bload<AWE_CPOL_STREAM>(r_cf, live ? o_in : kOob, so);
         if (IMG) {
-            sv = (live && xin) ? us[zo] : 0.f;
-            gv = (live && xin) ? gr[zo] : 0.f;
+            sv = bload<AWE_CPOL_STREAM>(r_us, live ? o_in : kOob, so);
+            gv = bload<AWE_CPOL_STREAM>(r_gr, live ? o_in : kOob, so);
         }
-        hv = (live && hxl) ? uch[zo] : 0.f;
+        hv = bload(r_uc, live ? o_hx : kOob, so);
     };
     fetch(zw);
     for (int i = 0; i < zchunk; ++i) {
@@ -256,7 +317,7 @@ step2d(StepArgs a, StencilCoef k, Geo2 g, int zchunk) {
         q[NQ - 1] = fr;
         lds[b][w][M + tx] = q[M];
         if (hl || hr) lds[b][w][hlx] = hv;
-        const float p = pv, c = cv, s = sv, gg = gv;
+        const float p = pv, c = cv, s = sv, gg = gv, ezv = ezn;
         if (i + 1 < zchunk) fetch(z + 1);
         lds_barrier();
         if (z < zend) {
@@ -267,14 +328,11 @@ step2d(StepArgs a, StencilCoef k, Geo2 g, int zchunk) {
                 lap += k.cz[kk] * (q[M - kk] + q[M + kk]);
                 lap += k.cx[kk] * (lds[b][w][lx - kk] + lds[b][w][lx + kk]);
             }
-            const float ezv = a.eta_z[z];
             const float u0 = q[M];
             const float av = (ezv + exv) * c * k.inv_dt;
             const float t = c * lap + av * (p - u0);
-            if (xin) {
-                out[(int64_t)z * sz] = (u0 - p) + u0 + t;
-                if (IMG) gr[(int64_t)z * sz] = gg + s * t;
-            }
+            bstore<AWE_CPOL_STREAM>(r_out, (u0 - p) + u0 + t, o_in, soff(z));
+            if (IMG) bstore<AWE_CPOL_STREAM>(r_gr, gg + s * t, o_in, soff(z));
         }
     }
 }
@@ -286,37 +344,33 @@ step2d(StepArgs a, StencilCoef k, Geo2 g, int zchunk) {
 // ---------------------------------------------------------------------------
 template <int M, bool IMG>
 hipError_t launch3(int cfg, const Layout& L, const StencilCoef& k, const StepArgs& a, int zchunk, hipStream_t s) {
-    Geo3 g{(int32_t)L.n[0], (int32_t)L.n[1], (int32_t)L.n[2], L.sy, L.sz, L.origin};
-    const unsigned gx = (unsigned)((L.n[2] + kTileX - 1) / kTileX);
-    const unsigned gz = (unsigned)((L.n[0] + zchunk - 1) / zchunk);
+    const int ty = tile_rows(3, cfg);
+    Geo3 g{(int32_t)L.n[0], (int32_t)L.n[1], (int32_t)L.n[2], L.sy, L.sz, L.origin, 0, 0, 0, L.total};
+    g.gx = (uint32_t)((L.n[2] + kTileX - 1) / kTileX);
+    g.gy = (uint32_t)((L.n[1] + ty - 1) / ty);
+    const uint32_t gz = (uint32_t)((L.n[0] + zchunk - 1) / zchunk);
+    g.ntiles = g.gx * g.gy * gz;
+    const dim3 grid((g.ntiles + kXcds - 1) / kXcds * kXcds);   // a multiple of the XCD count
     switch (cfg) {
-        case 0: {   // 64 x 16 tile, 256 threads, 4 rows per thread
-            dim3 grid(gx, (unsigned)((L.n[1] + 15) / 16), gz);
+        case 0:     // 64 x 16 tile, 256 threads, 4 rows per thread
             hipLaunchKernelGGL((step3d<M, 4, 4, IMG>), grid, dim3(kTileX, 4), 0, s, a, k, g, zchunk);
             break;
-        }
-        case 1: {   // 64 x 8 tile, 256 threads, 2 rows per thread
-            dim3 grid(gx, (unsigned)((L.n[1] + 7) / 8), gz);
+        case 1:     // 64 x 8 tile, 256 threads, 2 rows per thread
             hipLaunchKernelGGL((step3d<M, 4, 2, IMG>), grid, dim3(kTileX, 4), 0, s, a, k, g, zchunk);
             break;
-        }
-        case 2: {   // 64 x 32 tile, 512 threads, 4 rows per thread
-            dim3 grid(gx, (unsigned)((L.n[1] + 31) / 32), gz);
+        case 2:     // 64 x 32 tile, 512 threads, 4 rows per thread
             hipLaunchKernelGGL((step3d<M, 8, 4, IMG>), grid, dim3(kTileX, 8), 0, s, a, k, g, zchunk);
             break;
-        }
-        default: {  // 64 x 16 tile, 512 threads, 2 rows per thread
-            dim3 grid(gx, (unsigned)((L.n[1] + 15) / 16), gz);
+        default:    // 64 x 16 tile, 512 threads, 2 rows per thread
             hipLaunchKernelGGL((step3d<M, 8, 2, IMG>), grid, dim3(kTileX, 8), 0, s, a, k, g, zchunk);
             break;
-        }
     }
     return hipGetLastError();
 }
 
 template <int M, bool IMG>
 hipError_t launch2(int cfg, const Layout& L, const StencilCoef& k, const StepArgs& a, int zchunk, hipStream_t s) {
-    Geo2 g{(int32_t)L.n[0], (int32_t)L.n[2], L.sz, L.origin};
+    Geo2 g{(int32_t)L.n[0], (int32_t)L.n[2], L.sz, L.origin, L.total};
     const unsigned gx = (unsigned)((L.n[2] + kTileX - 1) / kTileX);
     const int nw = (cfg == 0) ? 4 : 1;
     const int64_t per_block = (int64_t)nw * zchunk;
@@ -356,6 +410,11 @@ int tile_rows(int ndim, int cfg) {
 hipError_t launch_step(const Layout& L, const StencilCoef& k, const StepArgs& a, bool imaging, int cfg,
                        int zchunk, hipStream_t s) {
     if (zchunk < 1 || cfg < 0 || cfg >= num_tile_cfgs(L.ndim)) return hipErrorInvalidValue;
+    // a workgroup's slab (zchunk + 2M planes) must be addressable with 31-bit
+    // byte offsets; tiling never changes results, so shorten the chunk if not
+    const int64_t max_planes = 0x7FFFFFF0ll / (4 * L.sz);
+    if (max_planes < 2 * L.half + 2) return hipErrorInvalidValue;
+    if (zchunk > max_planes - 2 * L.half - 1) zchunk = (int)(max_planes - 2 * L.half - 1);
     return imaging ? dispatch<true>(L, k, a, cfg, zchunk, s) : dispatch<false>(L, k, a, cfg, zchunk, s);
 }
 

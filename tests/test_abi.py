@@ -13,7 +13,7 @@ from paper_1608_08658_amd import _lib
 def test_library_exports_every_declared_symbol():
     names = _lib.header_symbols()
     assert len(names) >= 20
-    handle = C.CDLL(_lib.LIB_PATH)
+    handle = awe.lib()          # loads torch's HIP runtime first, then libawe.so
     missing = [n for n in names if not hasattr(handle, n)]
     assert not missing, missing
     # and the binding's table covers exactly the header

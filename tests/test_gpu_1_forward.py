@@ -150,3 +150,45 @@ def test_full_size_state_steps_sampled():
         scale = max(abs(want), 1e-3 * np.max(np.abs(u0)))
         log(f"  point {p}: gpu {got:.7e} oracle {want:.7e}")
         assert abs(got - want) <= 1e-5 * scale, p
+
+
+def _forward_with_env(monkeypatch, shot, dt, env):
+    for k, v in env.items():
+        if v is None:
+            monkeypatch.delenv(k, raising=False)
+        else:
+            monkeypatch.setenv(k, v)
+    plan = gpu_plan(shot, dt)
+    plan.set_model(dev(shot.m))
+    tr = host(plan.forward(dev(shot.wavelet(dt))))
+    u, _ = plan.get_state()
+    plan.close()
+    return tr, host(u)
+
+
+def test_every_launch_shape_is_bitwise_identical(monkeypatch):
+    # Tiling changes where a neighbour value comes from (registers or LDS),
+    # never the arithmetic of a point: all shapes agree bit for bit.
+    shot = small_3d_shot(310, 8, nt=40)
+    dt = shot_dt(shot)
+    ref = None
+    for cfg in ("0,7", "1,16", "2,33", "3,100", "3,56"):
+        out = _forward_with_env(monkeypatch, shot, dt, {"AWE_TILE": cfg})
+        if ref is None:
+            ref = out
+        else:
+            assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1]), cfg
+
+
+def test_autotuned_plan_matches_forced_shape(monkeypatch):
+    # 140^3 + 2 x 12 layer = 164^3 padded (> 4M points): the plan autotunes.
+    rng = np.random.default_rng(5)
+    shape = (140, 140, 140)
+    v = synth.layered_velocity(shape, rng, nlayers=(3, 5))
+    shot = synth.Shot("tune-140", shape, (10.0,) * 3, 8, 12, 30, 1.0 / v ** 2,
+                      np.array([[300.0, 700.0, 700.0]]), np.array([[25.0, 100.0 + 7 * i, 900.0] for i in range(50)]),
+                      20.0, damp_vref=float(v.min()))
+    dt = shot_dt(shot)
+    tuned = _forward_with_env(monkeypatch, shot, dt, {"AWE_TILE": None, "AWE_AUTOTUNE": None})
+    forced = _forward_with_env(monkeypatch, shot, dt, {"AWE_TILE": "1,28"})
+    assert np.array_equal(tuned[0], forced[0]) and np.array_equal(tuned[1], forced[1])

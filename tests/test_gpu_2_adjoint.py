@@ -213,3 +213,21 @@ def test_misfit_matches_numpy():
     ref = 0.5 * np.sum(r32 * r32)
     assert phi == pytest.approx(ref, rel=1e-12)
     assert np.array_equal(host(r), (a - b).astype(np.float64))
+
+
+def test_gradient_bitwise_across_launch_shapes(monkeypatch):
+    import paper_1608_08658_amd as awe
+    shot = small_3d_shot(610, 8, nt=40)
+    dt, w, d_obs = _gradient_case(shot, 8)
+    outs = []
+    for cfg in ("0,9", "1,31", "3,56"):
+        monkeypatch.setenv("AWE_TILE", cfg)
+        plan = gpu_plan(shot, dt)
+        plan.set_model(dev(shot.m))
+        tr = plan.forward(dev(w), ckpt_every=8)
+        _, resid = awe.misfit(tr, dev(d_obs))
+        _, g = plan.adjoint(resid, want_src_adj=False, want_grad=True)
+        outs.append(host(g))
+        plan.close()
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
