@@ -36,6 +36,29 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+PROFILE = os.path.join(ROOT, "profiles", "step3d_o8_336cube_forward.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_1608_08658_amd", "csrc", "kernels_stencil.hip")
+
+
+def profiled_traffic(shape):
+    """HBM bytes per stencil launch from the committed rocprofv3 counter
+    summary, or None when the kernel source or launch shape has changed
+    since the counters were taken."""
+    import hashlib
+    try:
+        facts = {}
+        for line in open(PROFILE):
+            if ":" in line and line.startswith("    ") and not line.strip().startswith(("cd ", "|")):
+                k, v = line.strip().split(":", 1)
+                facts[k.strip()] = v.strip()
+        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        if facts.get("source_sha256") != sha or facts.get("launch_shape") != f"{shape[0]},{shape[1]}":
+            return None
+        return float(facts["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(shot, dt, steps):
     """The FP64 oracle, untuned, on `steps` time steps of the same grid."""
     import oracle
@@ -83,6 +106,8 @@ def main():
                     nt=shot.nt, src_coords=shot.src_coords, rec_coords=shot.rec_coords,
                     damp_power=shot.damp_power, damp_R=shot.damp_R, damp_vref=shot.damp_vref)
     npad = int(np.prod(plan.padded))
+    shape_cfg, shape_zc = plan.info()["forward_shape"]
+    log(f"stencil launch shape: workgroup configuration {shape_cfg}, {shape_zc} z planes per workgroup")
     m = torch.tensor(shot.m, dtype=torch.float32, device="cuda")
     w = torch.tensor(shot.wavelet(dt), dtype=torch.float32, device="cuda")
     traces = torch.empty((shot.nt, len(shot.rec_coords)), dtype=torch.float32, device="cuda")
@@ -142,6 +167,7 @@ def main():
         base = cpu_baseline(shot, dt, args.cpu_steps)
         log(f"  {base['value'] / 1e6:.2f} Mpt/s in {base['seconds']} s")
 
+    traffic = profiled_traffic((shape_cfg, shape_zc))
     out = {
         "metric": "grid-pt updates/s",
         "value": value,
@@ -164,8 +190,11 @@ def main():
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
+            "algorithmic_bytes_per_launch": BYTES_PER_UPDATE * npad,
             "kernel": "step3d<M=4> (forward stencil)", "avg_launch_us": kern_s * 1e6,
+            "launch_shape": {"workgroup_cfg": shape_cfg, "zchunk": shape_zc},
             "bytes_per_update": BYTES_PER_UPDATE, "updates_per_launch": npad,
         },
         "cpu_baseline": base,

@@ -123,8 +123,11 @@ awe_status awe_footprint(const awe_geometry* g, int32_t ckpt_every, uint64_t* by
 awe_status awe_plan_create(const awe_geometry* g, awe_plan* out);
 awe_status awe_plan_destroy(awe_plan plan);
 
-/* Padded grid of a plan: out_host[0..2] = padded points per axis (1 beyond
- * ndim), out_host[3] = device bytes currently held. */
+/* Facts about a plan: out_host[0..2] = padded points per axis (1 beyond
+ * ndim), out_host[3] = device bytes currently held, out_host[4..5] = launch
+ * shape (workgroup configuration, z planes per workgroup) of the forward
+ * stencil and out_host[6..7] that of the adjoint stencil with imaging.
+ * out_host must hold 8 values. */
 awe_status awe_plan_info(awe_plan plan, int64_t* out_host);
 
 /*

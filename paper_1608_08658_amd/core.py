@@ -142,9 +142,10 @@ class Plan:
             pass
 
     def info(self):
-        out = (C.c_int64 * 4)()
+        out = (C.c_int64 * 8)()
         check(lib().awe_plan_info(self.handle, out))
-        return {"padded": tuple(out[:self.ndim]), "bytes": out[3]}
+        return {"padded": tuple(out[:self.ndim]), "bytes": out[3], "forward_shape": (out[4], out[5]),
+                "imaging_shape": (out[6], out[7])}
 
     def set_model(self, m):
         check(lib().awe_set_model(self.handle, _ptr(m, "m", self.shape), _stream()))

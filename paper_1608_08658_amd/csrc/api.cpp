@@ -94,6 +94,10 @@ awe_status awe_plan_info(awe_plan plan, int64_t* out) {
     out[1] = plan->g.ndim == 3 ? plan->pad[1] : plan->pad[2];
     out[2] = plan->g.ndim == 3 ? plan->pad[2] : 1;
     out[3] = (int64_t)plan->held;
+    out[4] = plan->fwd_shape.cfg;
+    out[5] = plan->fwd_shape.zchunk;
+    out[6] = plan->img_shape.cfg;
+    out[7] = plan->img_shape.zchunk;
     return AWE_OK;
 }
 

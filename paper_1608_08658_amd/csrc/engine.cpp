@@ -424,25 +424,31 @@ awe_status Plan::tune(bool img, hipStream_t user_stream) {
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     awe_status st = AWE_OK;
-    float best_ms = 1e30f;
-    LaunchShape best = shape;
     StepArgs a = img ? StepArgs{mu0, mu1, mu1, coef, d_ez, d_ey, d_ex, w0, grad}
                      : StepArgs{w0, w1, w1, coef, d_ez, d_ey, d_ex, nullptr, nullptr};
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
-    for (size_t i = 0; e == hipSuccess && i < cand.size(); ++i) {
-        for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch_step(L, k, a, img, cand[i].cfg, cand[i].zchunk, s);
-        if (e == hipSuccess) e = hipEventRecord(e0, s);
-        for (int w = 0; w < 6 && e == hipSuccess; ++w) e = launch_step(L, k, a, img, cand[i].cfg, cand[i].zchunk, s);
-        if (e == hipSuccess) e = hipEventRecord(e1, s);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e == hipSuccess && ms < best_ms) {
-            best_ms = ms;
-            best = cand[i];
+    // three interleaved rounds; a candidate's time is its fastest round
+    std::vector<float> best_of(cand.size(), 1e30f);
+    for (int round = 0; round < 3 && e == hipSuccess; ++round) {
+        for (size_t i = 0; e == hipSuccess && i < cand.size(); ++i) {
+            e = launch_step(L, k, a, img, cand[i].cfg, cand[i].zchunk, s);
+            if (e == hipSuccess) e = hipEventRecord(e0, s);
+            for (int w = 0; w < 5 && e == hipSuccess; ++w) e = launch_step(L, k, a, img, cand[i].cfg, cand[i].zchunk, s);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess) best_of[i] = std::min(best_of[i], ms);
         }
     }
+    LaunchShape best = shape;
+    float best_ms = 1e30f;
+    for (size_t i = 0; i < cand.size(); ++i)
+        if (best_of[i] < best_ms) {
+            best_ms = best_of[i];
+            best = cand[i];
+        }
     if (e != hipSuccess) st = fail(AWE_EHIP, "autotune: %s", hipGetErrorString(e));
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
