@@ -77,6 +77,72 @@ def cpu_baseline(shot, dt, steps):
             "seconds": round(t, 3)}
 
 
+def bench_gradient(torch, awe, synth, n=400, nt=2000):
+    """FWI gradient of the L2 trace misfit: 3-D, n^3 + 40-point layer, order 16,
+    h = 12.5 m, nt samples, checkpoints every 50 steps, layered model with a
+    +-10% Gaussian anomaly as the true model and its smoothed copy as the start.
+    Reports the gradient time against a plain forward of the same shot."""
+    shot = synth.config_3d_gradient(n=n, nt=nt)
+    K = shot.extra["checkpoint_every"]
+    m_true = shot.extra["m_true"]
+    vmax = float(np.sqrt(1.0 / min(shot.m.min(), m_true.min())))
+    dt = shot.dt_factor * awe.dt_max(3, shot.order, shot.spacing, vmax)
+    plan = awe.Plan(shape=shot.shape, spacing=shot.spacing, space_order=shot.order, nbl=shot.nbl, dt=dt,
+                    nt=shot.nt, src_coords=shot.src_coords, rec_coords=shot.rec_coords,
+                    damp_power=shot.damp_power, damp_R=shot.damp_R, damp_vref=shot.damp_vref)
+    npad = int(np.prod(plan.padded))
+    w = torch.tensor(shot.wavelet(dt), dtype=torch.float32, device="cuda")
+    plan.set_model(torch.tensor(m_true, dtype=torch.float32, device="cuda"))
+    d_obs = plan.forward(w).clone()
+    plan.set_model(torch.tensor(shot.m, dtype=torch.float32, device="cuda"))
+
+    def events():
+        return [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+
+    def gradient(ev):
+        ev[0].record()
+        tr = plan.forward(w, ckpt_every=K)
+        ev[1].record()
+        phi, resid = awe.misfit(tr, d_obs)
+        ev[2].record()
+        _, g = plan.adjoint(resid, want_src_adj=False, want_grad=True)
+        ev[3].record()
+        torch.cuda.synchronize()
+        return phi, g
+
+    gradient(events())                      # warm-up (tunes the imaging kernel's launch shape)
+    ev = events()
+    phi, g = gradient(ev)
+    t_fwd_ckpt = ev[0].elapsed_time(ev[1]) / 1e3
+    t_adj = ev[2].elapsed_time(ev[3]) / 1e3
+    t_grad = ev[0].elapsed_time(ev[3]) / 1e3
+    f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    f0.record()
+    plan.forward(w)
+    f1.record()
+    torch.cuda.synchronize()
+    t_fwd = f0.elapsed_time(f1) / 1e3
+    info = plan.info()
+    finite = bool(torch.isfinite(g).all().item())
+    plan.close()
+    upd = npad * (shot.nt - 1)
+    log(f"gradient {shot.name}: {t_grad:.3f} s (forward+checkpoints {t_fwd_ckpt:.3f} s, adjoint+recompute "
+        f"{t_adj:.3f} s), plain forward {t_fwd:.3f} s, ratio {t_grad / t_fwd:.2f}, phi {phi:.4e}, finite={finite}")
+    return {
+        "workload": f"3-D FWI gradient, {n}^3 physical + 40-point layer ({'x'.join(map(str, plan.padded))} "
+                    f"computed), order 16, {shot.nt} samples, checkpoints every {K} steps, layered model with "
+                    f"a Gaussian anomaly, smoothed start, {len(shot.rec_coords)} receivers",
+        "gradient_s": t_grad, "forward_with_checkpoints_s": t_fwd_ckpt, "adjoint_with_recompute_s": t_adj,
+        "plain_forward_s": t_fwd, "gradient_over_forward": t_grad / t_fwd,
+        "algorithmic_gradient_over_forward": 60.0 / 16.0,
+        "gradient_updates_per_s": 3 * upd / t_grad,
+        "gradient_algorithmic_GBps": 60.0 * upd / t_grad / 1e9,
+        "device_bytes": info["bytes"], "launch_shapes": {"forward": info["forward_shape"],
+                                                         "imaging": info["imaging_shape"]},
+        "finite": finite,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +151,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=4, help="oracle time steps for the CPU baseline (0 = skip)")
     ap.add_argument("--n", type=int, default=256, help="physical grid points per axis")
     ap.add_argument("--nt", type=int, default=1000)
+    ap.add_argument("--gradient-n", type=int, default=400,
+                    help="physical points per axis of the gradient workload (0 = skip it)")
     ap.add_argument("--copy-ref-mb", type=int, default=0,
                     help="also run a plain device-to-device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -161,6 +229,11 @@ def main():
         log(f"reference copy: {args.copy_ref_mb} MiB read + written, 3 times")
         del src, dst
 
+    grad = None
+    if args.gradient_n > 0:
+        log("gradient workload ...")
+        grad = bench_gradient(torch, awe, synth, n=args.gradient_n)
+
     base = None
     if args.cpu_steps > 0:
         log(f"CPU oracle baseline: {args.cpu_steps} steps ...")
@@ -198,6 +271,7 @@ def main():
             "bytes_per_update": BYTES_PER_UPDATE, "updates_per_launch": npad,
         },
         "cpu_baseline": base,
+        "gradient": grad,
         "setup_s": round(setup_s, 3),
         "traces_finite": finite,
     }

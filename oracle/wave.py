@@ -78,9 +78,12 @@ class Problem:
 class Operator:
     """The discrete forward/adjoint pair for one model."""
 
-    def __init__(self, problem: Problem, m: np.ndarray, check_cfl: bool = True):
+    def __init__(self, problem: Problem, m: np.ndarray, check_cfl: bool = True, backend: str = "numpy"):
         p = problem
         self.p = p
+        if backend not in ("numpy", "c") or (backend == "c" and p.periodic):
+            raise ValueError("backend is 'numpy' or 'c' (the C step has no periodic option)")
+        self.backend = backend
         m = np.asarray(m, dtype=np.float64)
         if m.shape != p.shape:
             raise ValueError(f"model shape {m.shape} != problem shape {p.shape}")
@@ -105,6 +108,11 @@ class Operator:
 
     def step(self, u, u_prev, q_n=None):
         """u[n+1] from u[n], u[n-1] and the wavelet sample q[n] (one per source)."""
+        if self.backend == "c":
+            extra = None
+            if self.src is not None and q_n is not None:
+                extra = spread(self.p.padded_shape, *self.src, q_n)
+            return self._cstep(u, u_prev, extra, self.vol)
         rhs = self._lap(u)
         if self.src is not None and q_n is not None:
             rhs = rhs + spread(self.p.padded_shape, *self.src, q_n) / self.vol
@@ -112,10 +120,23 @@ class Operator:
 
     def adjoint_step(self, mu1, mu2, y_n=None):
         """mu[n] from mu[n+1], mu[n+2] and the receiver samples y[n]."""
+        if self.backend == "c":
+            extra = None
+            if self.rec is not None and y_n is not None:
+                extra = spread(self.p.padded_shape, *self.rec, y_n)
+            return self._cstep(mu1, mu2, extra, 1.0)
         rhs = self._lap(mu1)
         if self.rec is not None and y_n is not None:
             rhs = rhs + spread(self.p.padded_shape, *self.rec, y_n)
         return self.A * mu1 - self.B * mu2 + self.C * rhs
+
+    def _cstep(self, u, up, extra, div):
+        from . import cref
+        from .fd import weights_f64
+        if not hasattr(self, "_w"):
+            self._w = weights_f64(self.p.order)
+            self.A, self.B, self.C = (np.ascontiguousarray(x) for x in (self.A, self.B, self.C))
+        return cref.step(u, up, self.A, self.B, self.C, extra, div, self.p.spacing, self._w)
 
     def record(self, u):
         if self.rec is None:
