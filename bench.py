@@ -153,6 +153,7 @@ def main():
     ap.add_argument("--nt", type=int, default=1000)
     ap.add_argument("--gradient-n", type=int, default=400,
                     help="physical points per axis of the gradient workload (0 = skip it)")
+    ap.add_argument("--gradient-nt", type=int, default=2000, help="time samples of the gradient workload")
     ap.add_argument("--copy-ref-mb", type=int, default=0,
                     help="also run a plain device-to-device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -232,7 +233,7 @@ def main():
     grad = None
     if args.gradient_n > 0:
         log("gradient workload ...")
-        grad = bench_gradient(torch, awe, synth, n=args.gradient_n)
+        grad = bench_gradient(torch, awe, synth, n=args.gradient_n, nt=args.gradient_nt)
 
     base = None
     if args.cpu_steps > 0:

@@ -24,10 +24,23 @@
 //   * each thread owns RY consecutive y rows, so y-neighbours inside its own
 //     rows come from registers.
 // 2-D uses the same scheme with a 64-point x row in LDS and no y axis.
+#include <type_traits>
+#include <utility>
+
 #include "awe_internal.hpp"
 
 namespace awe {
 namespace {
+
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+// f(integral_constant<int, 0>) ... f(integral_constant<int, N-1>), unrolled.
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
 
 // s_waitcnt vmcnt(0) (gfx9 encoding: expcnt and lgkmcnt left at their maxima).
 // Used once after the queue is filled: with no load of the prologue still in
@@ -95,7 +108,11 @@ template <int M, int BY, int RY, bool IMG>
 __global__ void __launch_bounds__(kTileX * BY)
 step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk) {
     constexpr int TY = BY * RY;
-    constexpr int LW = kTileX + 2 * M;
+    // LDS row pitch of 128 dwords (two 64-dword units): every y-neighbour pair
+    // (y-k, y+k) is then one ds_read2st64 with immediate offsets, instead of
+    // an address computation per pair at 80-dword pitches
+    constexpr int LW = 128;
+    static_assert(kTileX + 2 * M <= LW, "halo wider than the LDS row");
     constexpr int LH = TY + 2 * M;
     constexpr int NQ = 2 * M + 1;
     constexpr int NH = (2 * M + BY - 1) / BY;     // y-halo rows per thread row
@@ -193,18 +210,20 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk) {
     };
     fetch(z0);
 
-    for (int z = z0; z < z1; ++z) {
+    // One plane.  The z-queue is never shifted: in iteration z the logical
+    // slot j (plane z - M + j) lives in physical slot (j + PH) % NQ, with PH
+    // advancing by one per plane.  The loop is unrolled NQ times so PH is a
+    // compile-time constant and no register moves are needed.
+    auto one_plane = [&](auto ph, int z) {
+        constexpr int PH = decltype(ph)::value;
+        auto Q = [&](int r, int j) -> float& { return q[r][(j + PH) % NQ]; };
         const int b = (z - z0) & 1;
 #pragma unroll
-        for (int r = 0; r < RY; ++r) {
-#pragma unroll
-            for (int j = 0; j < NQ - 1; ++j) q[r][j] = q[r][j + 1];
-            q[r][NQ - 1] = fr[r];
-        }
+        for (int r = 0; r < RY; ++r) Q(r, NQ - 1) = fr[r];
         // stage plane z in LDS
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-            lds[b][M + ty * RY + r][M + tx] = q[r][M];
+            lds[b][M + ty * RY + r][M + tx] = Q(r, M);
             if (hl || hr) lds[b][M + ty * RY + r][hlx] = hxv[r];
         }
 #pragma unroll
@@ -223,25 +242,49 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk) {
         lds_barrier();
 
         const uint32_t so = soff(z);
+        // One LDS offset per thread and one per row, hidden from the optimiser
+        // (the empty asm emits nothing): every neighbour is then an immediate
+        // offset from them (x: 0..2M dwords, y: multiples of LW), so each pair
+        // of reads is one ds_read2 / ds_read2st64 with no address arithmetic.
+        int lofs = (b * LH + ty * RY) * LW + tx + M;   // (row ly - M, column lx)
+        asm volatile("" : "+v"(lofs));
+        int lrow[RY];                                  // (row ly, column lx - M)
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-            const int ly = M + ty * RY + r;
-            const int lx = M + tx;
-            float lap = k.c0 * q[r][M];
+            lrow[r] = lofs + (r + M) * LW - M;
+            asm volatile("" : "+v"(lrow[r]));
+        }
+        const float* lflat = &lds[0][0][0];
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            const float* ly = lflat + lofs + (r + M) * LW;   // this point, y pairs
+            const float* lx = lflat + lrow[r] + M;           // this point, x pairs
+            float lap = k.c0 * Q(r, M);
 #pragma unroll
             for (int kk = 1; kk <= M; ++kk) {
-                const float yu = (r - kk >= 0) ? q[(r - kk) >= 0 ? (r - kk) : 0][M] : lds[b][ly - kk][lx];
-                const float yd = (r + kk < RY) ? q[(r + kk) < RY ? (r + kk) : 0][M] : lds[b][ly + kk][lx];
-                lap += k.cz[kk] * (q[r][M - kk] + q[r][M + kk]);
+                const float yu = (r - kk >= 0) ? Q((r - kk) >= 0 ? (r - kk) : 0, M) : ly[-kk * LW];
+                const float yd = (r + kk < RY) ? Q((r + kk) < RY ? (r + kk) : 0, M) : ly[kk * LW];
+                lap += k.cz[kk] * (Q(r, M - kk) + Q(r, M + kk));
                 lap += k.cy[kk] * (yu + yd);
-                lap += k.cx[kk] * (lds[b][ly][lx - kk] + lds[b][ly][lx + kk]);
+                lap += k.cx[kk] * (lx[-kk] + lx[kk]);
             }
-            const float u0 = q[r][M];
+            const float u0 = Q(r, M);
             const float av = (ezv + eyv[r] + exv) * c[r] * k.inv_dt;
             const float t = c[r] * lap + av * (p[r] - u0);
             bstore<AWE_CPOL_STREAM>(r_out, (u0 - p[r]) + u0 + t, o_in[r], so);
             if (IMG) bstore<AWE_CPOL_STREAM>(r_gr, gg[r] + s[r] * t, o_in[r], so);
         }
+    };
+    // before plane z0 the queue holds planes z0-M .. z0+M-1 in physical slots
+    // 1..NQ-1, i.e. logical slot j sits in (j + 1) % NQ: the first plane has PH = 1
+    int z = z0;
+    for (;;) {
+        static_for<NQ>([&](auto s_) {
+            constexpr int PH = (decltype(s_)::value + 1) % NQ;
+            if (z < z1) one_plane(std::integral_constant<int, PH>{}, z);
+            ++z;
+        });
+        if (z >= z1) break;
     }
 }
 
@@ -402,7 +445,7 @@ int num_tile_cfgs(int ndim) { return ndim == 3 ? 4 : 2; }
 int tile_rows(int ndim, int cfg) {
     if (ndim == 3) {
         static const int rows[4] = {16, 8, 32, 16};
-        return rows[cfg & 3];
+        return rows[cfg];
     }
     return cfg == 0 ? 4 : 1;
 }
