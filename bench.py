@@ -143,6 +143,109 @@ def bench_gradient(torch, awe, synth, n=400, nt=2000):
     }
 
 
+def bench_serve(awe, synth, count=64, scale=0.5, seed=4, max_active=16, chunk=64):
+    """Continuous-batching shot server under Poisson load.  First the
+    saturation rate mu (every request submitted at once), then Poisson
+    arrivals at 0.5, 0.8 and 0.95 mu with p50/p99 latency (result on the
+    host minus arrival, queueing included)."""
+    reqs = synth.serving_requests(seed, count, scale=scale)
+    prepared = []
+    for r in reqs:
+        dt = r.dt_factor * awe.dt_max(r.ndim, r.order, r.spacing, r.vmax)
+        g = awe.make_geometry(shape=r.shape, spacing=r.spacing, space_order=r.order, nbl=r.nbl, dt=dt, nt=r.nt,
+                              src_coords=r.src_coords, rec_coords=r.rec_coords, damp_power=r.damp_power,
+                              damp_R=r.damp_R, damp_vref=r.damp_vref)
+        npad = int(np.prod([n + 2 * r.nbl for n in r.shape]))
+        prepared.append((g, r.m.astype(np.float32), r.wavelet(dt).astype(np.float32), npad * (r.nt - 1)))
+    work = sum(p[3] for p in prepared)
+
+    def run(rate):
+        srv = awe.Server(hbm_fraction=0.9, chunk_steps=chunk, max_active=max_active)
+        rng = np.random.default_rng(seed + 1)
+        tickets = []
+        t0 = time.perf_counter()
+        t_next = 0.0
+        for g, m, w, _ in prepared:
+            if rate:
+                t_next += rng.exponential(1.0 / rate)
+                delay = t0 + t_next - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+            tickets.append(srv.submit(g, m, w)[0])
+        for t in tickets:
+            srv.wait(t, timeout=600)
+        times = np.array([srv.poll(t)[1] for t in tickets])
+        srv.close()
+        lat = times[:, 3] - times[:, 0]
+        span = times[:, 3].max() - times[:, 0].min()
+        return {"offered_per_s": rate, "shots_per_s": len(tickets) / span, "p50_latency_s": float(np.percentile(lat, 50)),
+                "p99_latency_s": float(np.percentile(lat, 99)), "mean_latency_s": float(lat.mean()),
+                "grid_pt_updates_per_s": work / span, "wall_s": span}
+
+    sat = run(None)
+    mu = sat["shots_per_s"]
+    log(f"serving: saturation {mu:.2f} shots/s, {sat['grid_pt_updates_per_s'] / 1e9:.1f} Gpt/s")
+    points = []
+    for f in (0.5, 0.8, 0.95):
+        res = run(f * mu)
+        res["load"] = f
+        points.append(res)
+        log(f"serving at {f:.2f} mu: {res['shots_per_s']:.2f} shots/s, p50 {res['p50_latency_s'] * 1e3:.1f} ms, "
+            f"p99 {res['p99_latency_s'] * 1e3:.1f} ms")
+    return {"workload": f"{count} seeded shot requests (2-D n^2 and 3-D n^3 mix, orders 4/8/16, layered models, "
+                        f"sizes and step counts scaled by {scale}), chunk {chunk} steps, up to {max_active} running",
+            "requests": count, "saturation": sat, "poisson": points}
+
+
+def bench_served_gradient(torch, awe, synth, n=300, nt=1500, nshots=32):
+    """Per-shot FWI gradients through the autograd Function, summed on the
+    device in fixed shot order, against a plain forward of the same shot."""
+    shots = synth.config_served_gradient(n=n, nt=nt, nshots=nshots)
+    K = shots[0].extra["checkpoint_every"]
+    m_true = shots[0].extra["m_true"]
+    vmax = float(np.sqrt(1.0 / min(shots[0].m.min(), m_true.min())))
+    dt = shots[0].dt_factor * awe.dt_max(3, shots[0].order, shots[0].spacing, vmax)
+    m0 = torch.tensor(shots[0].m, dtype=torch.float32, device="cuda")
+    mt = torch.tensor(m_true, dtype=torch.float32, device="cuda")
+    total = torch.zeros_like(m0)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    t_grad, t_fwd = [], []
+    loss_sum = 0.0
+    for i, sh in enumerate(shots):
+        plan = awe.Plan(shape=sh.shape, spacing=sh.spacing, space_order=sh.order, nbl=sh.nbl, dt=dt, nt=sh.nt,
+                        src_coords=sh.src_coords, rec_coords=sh.rec_coords, damp_power=sh.damp_power,
+                        damp_R=sh.damp_R, damp_vref=sh.damp_vref)
+        w = torch.tensor(sh.wavelet(dt), dtype=torch.float32, device="cuda")
+        plan.set_model(mt)
+        d_obs = plan.forward(w).clone()
+        m = m0.clone().requires_grad_(True)
+        ev[0].record()
+        tr = awe.Gradient.apply(m, w, plan, K)
+        loss = 0.5 * ((tr - d_obs) ** 2).sum()
+        loss.backward()
+        total += m.grad
+        ev[1].record()
+        torch.cuda.synchronize()
+        t_grad.append(ev[0].elapsed_time(ev[1]) / 1e3)
+        loss_sum += float(loss.detach())
+        ev[0].record()
+        plan.forward(w)
+        ev[1].record()
+        torch.cuda.synchronize()
+        t_fwd.append(ev[0].elapsed_time(ev[1]) / 1e3)
+        plan.close()
+        log(f"shot {i + 1}/{len(shots)}: gradient {t_grad[-1]:.3f} s, forward {t_fwd[-1]:.3f} s")
+    npad = (n + 80) ** 3
+    tg, tf = float(np.median(t_grad[1:] or t_grad)), float(np.median(t_fwd[1:] or t_fwd))
+    return {"workload": f"{nshots} shots on one {n}^3 layered model with an anomaly (+40-point layer), order 8, "
+                        f"{nt} samples, checkpoints every {K} steps, 4x8 surface sources, "
+                        f"{len(shots[0].rec_coords)} receivers, gradients via the autograd Function summed on device",
+            "shots": nshots, "total_gradient_s": float(sum(t_grad)), "median_gradient_s": tg,
+            "median_forward_s": tf, "gradient_over_forward": tg / tf, "algorithmic_gradient_over_forward": 3.75,
+            "gradient_algorithmic_GBps": 60.0 * npad * (nt - 1) / tg / 1e9,
+            "total_misfit": loss_sum, "gradient_finite": bool(torch.isfinite(total).all().item())}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,6 +257,10 @@ def main():
     ap.add_argument("--gradient-n", type=int, default=400,
                     help="physical points per axis of the gradient workload (0 = skip it)")
     ap.add_argument("--gradient-nt", type=int, default=2000, help="time samples of the gradient workload")
+    ap.add_argument("--serve-requests", type=int, default=64, help="requests in the serving run (0 = skip)")
+    ap.add_argument("--serve-scale", type=float, default=0.5, help="size/step scale of the serving mix")
+    ap.add_argument("--served-gradient-shots", type=int, default=0,
+                    help="shots of the 300^3 served-gradient workload (0 = skip; 32 is the full workload)")
     ap.add_argument("--copy-ref-mb", type=int, default=0,
                     help="also run a plain device-to-device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -235,6 +342,16 @@ def main():
         log("gradient workload ...")
         grad = bench_gradient(torch, awe, synth, n=args.gradient_n, nt=args.gradient_nt)
 
+    serve = None
+    if args.serve_requests > 0:
+        log("serving workload ...")
+        serve = bench_serve(awe, synth, count=args.serve_requests, scale=args.serve_scale)
+
+    shots = None
+    if args.served_gradient_shots > 0:
+        log("served-gradient workload ...")
+        shots = bench_served_gradient(torch, awe, synth, nshots=args.served_gradient_shots)
+
     base = None
     if args.cpu_steps > 0:
         log(f"CPU oracle baseline: {args.cpu_steps} steps ...")
@@ -273,6 +390,8 @@ def main():
         },
         "cpu_baseline": base,
         "gradient": grad,
+        "serving": serve,
+        "served_gradients": shots,
         "setup_s": round(setup_s, 3),
         "traces_finite": finite,
     }
