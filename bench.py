@@ -37,7 +37,7 @@ def log(msg):
 
 
 PROFILE = os.path.join(ROOT, "profiles", "step3d_o8_336cube_forward.md")
-KERNEL_SRC = os.path.join(ROOT, "paper_1608_08658_amd", "csrc", "kernels_stencil.hip")
+KERNEL_SRC = os.path.join(ROOT, "paper_1608_08658_amd", "csrc", "stencil_impl.hpp")
 
 
 def profiled_traffic(shape):
@@ -246,6 +246,34 @@ def bench_served_gradient(torch, awe, synth, n=300, nt=1500, nshots=32):
             "total_misfit": loss_sum, "gradient_finite": bool(torch.isfinite(total).all().item())}
 
 
+def bench_paper_example(torch, awe, synth):
+    """The paper's 3-D run (Sec. V.D): 281 x 281 x 150 computed points,
+    h = 15 m, order 14, 10 Hz Ricker, 1 s modelled, synthetic layered model."""
+    shot = synth.config_paper_example()
+    dt = shot.dt_factor * awe.dt_max(3, shot.order, shot.spacing, shot.vmax)
+    shot.nt = int(round(shot.extra["t_end"] / dt)) + 1
+    plan = awe.Plan(shape=shot.shape, spacing=shot.spacing, space_order=shot.order, nbl=shot.nbl, dt=dt, nt=shot.nt,
+                    src_coords=shot.src_coords, rec_coords=shot.rec_coords, damp_power=shot.damp_power,
+                    damp_R=shot.damp_R, damp_vref=shot.damp_vref)
+    plan.set_model(torch.tensor(shot.m, dtype=torch.float32, device="cuda"))
+    w = torch.tensor(shot.wavelet(dt), dtype=torch.float32, device="cuda")
+    plan.forward(w)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    tr = plan.forward(w)
+    ev[1].record()
+    torch.cuda.synchronize()
+    t = ev[0].elapsed_time(ev[1]) / 1e3
+    npad = int(np.prod(plan.padded))
+    finite = bool(torch.isfinite(tr).all().item())
+    plan.close()
+    log(f"paper example: {shot.nt} samples in {t * 1e3:.1f} ms, {npad * (shot.nt - 1) / t / 1e9:.1f} Gpt/s")
+    return {"workload": "the paper's 3-D run: 201x201x70 + 40-point layer (150x281x281 computed), h = 15 m, "
+                        "order 14, 10 Hz Ricker, 1 s modelled, synthetic layered model (the paper gives none)",
+            "nt": shot.nt, "dt": dt, "forward_s": t, "grid_pt_updates_per_s": npad * (shot.nt - 1) / t,
+            "algorithmic_GBps": 16.0 * npad * (shot.nt - 1) / t / 1e9, "finite": finite}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -342,6 +370,9 @@ def main():
         log("gradient workload ...")
         grad = bench_gradient(torch, awe, synth, n=args.gradient_n, nt=args.gradient_nt)
 
+    log("paper example workload ...")
+    paper = bench_paper_example(torch, awe, synth)
+
     serve = None
     if args.serve_requests > 0:
         log("serving workload ...")
@@ -390,6 +421,7 @@ def main():
         },
         "cpu_baseline": base,
         "gradient": grad,
+        "paper_example": paper,
         "serving": serve,
         "served_gradients": shots,
         "setup_s": round(setup_s, 3),

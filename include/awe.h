@@ -169,6 +169,21 @@ awe_status awe_forward(awe_plan plan, const float* wavelet_dev, float* traces_de
 awe_status awe_adjoint(awe_plan plan, const float* resid_dev, float* src_adj_dev,
                        float* grad_m_dev, awe_stream stream);
 
+/*
+ * Linearised (Born) modelling: traces_dev [nt][nrec] = J dm, the derivative
+ * of the forward traces with respect to the physical model in the direction
+ * dm_dev (physical shape).  Differentiating the scheme of awe_forward (with
+ * the absorbing layer fixed) gives a scattered field du driven by the
+ * background's second time difference:
+ *   du[n+1] = (2-a) du[n] - (1-a) du[n-1] + C L du[n] - (C/dt^2) dm (u[n+1] - 2u[n] + u[n-1]),
+ *   traces[n] = R du[n].
+ * Its adjoint is the gradient of awe_adjoint: <J dm, y> = <dm, J^T y>, the
+ * linear-algebra counterpart of Eq. (3).  Uses the model of awe_set_model and
+ * overwrites the plan's wavefield state (and any stored checkpoints).
+ */
+awe_status awe_born(awe_plan plan, const float* wavelet_dev, const float* dm_dev, float* traces_dev,
+                    awe_stream stream);
+
 /* The padded gradient of the last awe_adjoint that produced one
  * (padded shape, dense).  AWE_ESTATE if there is none. */
 awe_status awe_get_gradient_padded(awe_plan plan, float* g_pad_dev, awe_stream stream);

@@ -232,6 +232,34 @@ class Operator:
             out["grad_pad"] = -g / (p.dt * p.dt)
         return out
 
+    # -- Born (linearised) modelling --------------------------------------------
+    def born(self, wavelet, dm):
+        """J dm: the derivative of the traces with respect to the physical
+        model in the direction dm (the linear map whose adjoint is the
+        gradient of Eq. 3).  Differentiating the discrete scheme with eta fixed:
+            du[-1] = du[0] = 0,
+            du[n+1] = A du[n] - B du[n-1] + C L du[n]
+                      - (C / dt^2) dm_pad * (u[n+1] - 2 u[n] + u[n-1]),
+            dd[n] = R du[n],
+        with dm_pad the edge-replicated dm (the padding is linear in m).
+        Returns the traces [nt, nrec] of du."""
+        p = self.p
+        q = _as_2d(wavelet, p.nt)
+        dm_pad = pad_model(np.asarray(dm, dtype=np.float64), p.nbl)
+        shape = p.padded_shape
+        u, u_prev = np.zeros(shape), np.zeros(shape)
+        du, du_prev = np.zeros(shape), np.zeros(shape)
+        nrec = 0 if self.rec is None else self.rec[0].shape[0]
+        traces = np.zeros((p.nt, nrec))
+        for n in range(p.nt - 1):
+            u_next = self.step(u, u_prev, q[n] if q.shape[1] else None)
+            born_src = -(self.C / (p.dt * p.dt)) * dm_pad * (u_next - 2.0 * u + u_prev)
+            du_next = self.A * du - self.B * du_prev + self.C * self._lap(du) + born_src
+            u_prev, u = u, u_next
+            du_prev, du = du, du_next
+            traces[n + 1] = self.record(du)
+        return traces
+
     # -- FWI gradient ----------------------------------------------------------
     def gradient(self, wavelet, d_obs, checkpoint_every=None):
         """Misfit, physical and padded gradient, and the modelled traces."""

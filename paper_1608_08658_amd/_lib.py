@@ -47,6 +47,7 @@ _SIGNATURES = {
     "awe_set_model": (_I32, [_P, _P, _P]),
     "awe_forward": (_I32, [_P, _P, _P, _I32, _P]),
     "awe_adjoint": (_I32, [_P, _P, _P, _P, _P]),
+    "awe_born": (_I32, [_P, _P, _P, _P, _P]),
     "awe_get_gradient_padded": (_I32, [_P, _P, _P]),
     "awe_set_state": (_I32, [_P, _P, _P, _P]),
     "awe_step": (_I32, [_P, _I32, _I32, _P, _P, _P]),

@@ -20,7 +20,8 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libawe.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["kernels_stencil.hip", "kernels_aux.hip", "engine.cpp", "api.cpp", "server.cpp"]
+SOURCES = ["kernels_stencil_hi.hip", "kernels_stencil_lo.hip", "kernels_stencil.hip", "kernels_aux.hip",
+           "engine.cpp", "api.cpp", "server.cpp"]
 
 ARCH = "gfx950"
 FLAGS = [
@@ -56,7 +57,7 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     """Compile every source and link libawe.so; returns its path."""
     hipcc = _hipcc()
     os.makedirs(BUILD_DIR, exist_ok=True)
-    jobs = jobs or min(len(SOURCES), max(1, (os.cpu_count() or 2) // 2))
+    jobs = jobs or min(len(SOURCES), max(1, os.cpu_count() or 2))
     with concurrent.futures.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(lambda s: _compile(hipcc, s, verbose), SOURCES))
     tmp = OUT + ".tmp"

@@ -167,6 +167,15 @@ class Plan:
                                 _stream()))
         return src_adj, grad
 
+    def born(self, wavelet, dm, traces=None):
+        """J dm: linearised traces for a model perturbation dm (physical shape)."""
+        torch = _torch()
+        if traces is None:
+            traces = torch.empty((self.nt, self.nrec), dtype=torch.float32, device="cuda")
+        check(lib().awe_born(self.handle, _ptr(wavelet, "wavelet", (self.nt, self.nsrc), allow_none=self.nsrc == 0),
+                             _ptr(dm, "dm", self.shape), _ptr(traces, "traces", (self.nt, self.nrec)), _stream()))
+        return traces
+
     def gradient_padded(self):
         torch = _torch()
         out = torch.empty(self.padded, dtype=torch.float32, device="cuda")

@@ -116,6 +116,11 @@ awe_status awe_adjoint(awe_plan plan, const float* resid, float* src_adj, float*
     AWE_TRY(return plan->adjoint(resid, src_adj, grad_m, as_stream(s)));
 }
 
+awe_status awe_born(awe_plan plan, const float* wavelet, const float* dm, float* traces, awe_stream s) {
+    if (!plan) return fail(AWE_EINVAL, "plan is NULL");
+    AWE_TRY(return plan->born(wavelet, dm, traces, as_stream(s)));
+}
+
 awe_status awe_get_gradient_padded(awe_plan plan, float* g_pad, awe_stream s) {
     if (!plan || !g_pad) return fail(AWE_EINVAL, "NULL argument");
     if (!plan->have_grad) return fail(AWE_ESTATE, "no gradient has been computed on this plan");

@@ -29,14 +29,18 @@ struct Layout {
     int64_t index(int64_t z, int64_t y, int64_t x) const { return origin + z * sz + y * sy + x; }
 };
 
-// FD weights pre-scaled by 1 / h_a^2, and the time-step constant.
+// FD weights pre-scaled by 1 / h_a^2, and the time-step constants.
 struct StencilCoef {
     float cz[kMaxHalf + 1];
     float cy[kMaxHalf + 1];
     float cx[kMaxHalf + 1];
     float c0;                    // c_0 * sum_a 1 / h_a^2
     float inv_dt;
+    float inv_dt2;
 };
+
+// What a stencil launch does besides the update (see stencil_impl.hpp).
+enum StepMode { kStepPlain = 0, kStepImaging = 1, kStepBorn = 2, kStepSaveT = 3 };
 
 // Arguments of one stencil step.  out may alias up (in-place update): every
 // thread reads up at a point before it writes out at the same point, and no
@@ -49,13 +53,14 @@ struct StepArgs {
     const float* eta_z;          // per-axis damping tables (eta = sum of the three)
     const float* eta_y;
     const float* eta_x;
-    const float* usnap;          // imaging only: forward wavefield u[n]
-    float* grad;                 // imaging only: accumulates u[n] * (mu[n] - 2 mu[n+1] + mu[n+2])
+    const float* usnap;          // imaging: forward wavefield u[n]; born: dm on the padded grid
+    float* grad;                 // imaging: accumulates u[n] * (mu[n] - 2 mu[n+1] + mu[n+2]);
+                                 // save-t: receives t; born: the background's t (read)
 };
 
 // Kernel launchers (kernels_stencil.hip, kernels_aux.hip).  All return the
 // launch status; none synchronise.
-hipError_t launch_step(const Layout& L, const StencilCoef& k, const StepArgs& a, bool imaging,
+hipError_t launch_step(const Layout& L, const StencilCoef& k, const StepArgs& a, int mode,
                        int tile_cfg, int zchunk, hipStream_t s);
 int num_tile_cfgs(int ndim);
 int tile_rows(int ndim, int tile_cfg);   // y rows (3-D) or z chunks per block (2-D)
@@ -71,6 +76,8 @@ hipError_t launch_minmax(const float* m, int64_t n, float* partial /* [3 * block
 hipError_t launch_fold(float* grad_phys, const float* g, const Layout& L, const int64_t phys[3], int nbl,
                        float scale, hipStream_t s);
 hipError_t launch_pack(float* dense, const float* pitched, const Layout& L, float scale, hipStream_t s);
+hipError_t launch_pad(float* pitched, const float* m_phys, const Layout& L, const int64_t phys[3], int nbl,
+                      hipStream_t s);
 hipError_t launch_unpack(float* pitched, const float* dense, const Layout& L, hipStream_t s);
 hipError_t launch_misfit(const float* tr, const float* obs, int64_t n, float* resid, double* partial,
                          int blocks, double* result, hipStream_t s);

@@ -315,6 +315,7 @@ awe_status Plan::init(const awe_geometry* geo) {
         k.cy[j] = g.ndim == 3 ? (float)(c[j] / (hy * hy)) : 0.f;
     }
     k.inv_dt = (float)(1.0 / g.dt);
+    k.inv_dt2 = (float)(1.0 / (g.dt * g.dt));
 
     fwd_shape = img_shape = default_shape(L);
 
@@ -432,9 +433,9 @@ awe_status Plan::tune(bool img, hipStream_t user_stream) {
     std::vector<float> best_of(cand.size(), 1e30f);
     for (int round = 0; round < 3 && e == hipSuccess; ++round) {
         for (size_t i = 0; e == hipSuccess && i < cand.size(); ++i) {
-            e = launch_step(L, k, a, img, cand[i].cfg, cand[i].zchunk, s);
+            e = launch_step(L, k, a, img ? kStepImaging : kStepPlain, cand[i].cfg, cand[i].zchunk, s);
             if (e == hipSuccess) e = hipEventRecord(e0, s);
-            for (int w = 0; w < 5 && e == hipSuccess; ++w) e = launch_step(L, k, a, img, cand[i].cfg, cand[i].zchunk, s);
+            for (int w = 0; w < 5 && e == hipSuccess; ++w) e = launch_step(L, k, a, img ? kStepImaging : kStepPlain, cand[i].cfg, cand[i].zchunk, s);
             if (e == hipSuccess) e = hipEventRecord(e1, s);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0.f;
@@ -489,7 +490,7 @@ awe_status Plan::set_model(const float* m, hipStream_t s) {
 // One step of the recurrence from (uc, up) into out, then the point source.
 awe_status Plan::advance(const float* uc, const float* up, float* out, const float* q_row, hipStream_t s) {
     StepArgs a{uc, up, out, coef, d_ez, d_ey, d_ex, nullptr, nullptr};
-    AWE_HIP(launch_step(L, k, a, false, fwd_shape.cfg, fwd_shape.zchunk, s));
+    AWE_HIP(launch_step(L, k, a, kStepPlain, fwd_shape.cfg, fwd_shape.zchunk, s));
     if (q_row && g.nsrc > 0)
         AWE_HIP(launch_inject(out, coef, src_csr.node, src_csr.rowptr, src_csr.pt, src_csr.w, src_csr.nrows, q_row,
                               (float)(1.0 / vol), nullptr, nullptr, s));
@@ -579,6 +580,47 @@ awe_status Plan::step(int n0, int nsteps, const float* wavelet, float* traces, h
     return AWE_OK;
 }
 
+// Linearised (Born) modelling: J dm, the derivative of the traces with
+// respect to m in the direction dm.  The background u and the scattered field
+// du advance together: the background step also writes its second time
+// difference t = u[n+1] - 2u[n] + u[n-1] (cancellation-free, the injected
+// source included), and the scattered step adds -(C/dt^2) dm t.
+awe_status Plan::born(const float* wavelet, const float* dm_phys, float* traces, hipStream_t s) {
+    if (!model_set) return fail(AWE_ESTATE, "awe_set_model has not been called on this plan");
+    if (!dm_phys) return fail(AWE_EINVAL, "dm is NULL");
+    if (g.nsrc > 0 && !wavelet) return fail(AWE_EINVAL, "wavelet is NULL but nsrc > 0");
+    awe_status st;
+    if (!b_t && ((st = alloc_field(&b_t)) || (st = alloc_field(&b_du0)) || (st = alloc_field(&b_du1)) ||
+                 (st = alloc_field(&b_dm))))
+        return st;
+    AWE_HIP(launch_pad(b_dm, dm_phys, L, phys, g.nbl, s));
+    for (float* f : {w0, w1, b_du0, b_du1}) AWE_HIP(launch_fill(f, L.total, 0.f, s));
+    if (traces && g.nrec > 0) AWE_HIP(launch_fill(traces, g.nrec, 0.f, s));
+    have_ckpt = false;
+    cur = w0;
+    prev = w1;
+    float* dcur = b_du0;     // du[n]
+    float* dprev = b_du1;    // du[n-1], overwritten in place by du[n+1]
+    const int cfg = g.ndim == 3 ? 3 : 0;
+    const int zc = fwd_shape.zchunk;
+    for (int n = 0; n + 1 < g.nt; ++n) {
+        float* dst = const_cast<float*>(prev);          // in place over u[n-1]
+        StepArgs a{cur, prev, dst, coef, d_ez, d_ey, d_ex, nullptr, b_t};
+        AWE_HIP(launch_step(L, k, a, kStepSaveT, cfg, zc, s));
+        if (g.nsrc > 0)
+            AWE_HIP(launch_inject(dst, coef, src_csr.node, src_csr.rowptr, src_csr.pt, src_csr.w, src_csr.nrows,
+                                  wavelet + (size_t)n * g.nsrc, (float)(1.0 / vol), nullptr, b_t, s));
+        StepArgs b{dcur, dprev, dprev, coef, d_ez, d_ey, d_ex, b_dm, b_t};
+        AWE_HIP(launch_step(L, k, b, kStepBorn, cfg, zc, s));
+        if (traces && g.nrec > 0)
+            AWE_HIP(launch_sample(traces + (size_t)(n + 1) * g.nrec, dprev, rec_node, rec_w, g.nrec, corners, 1.f, s));
+        prev = cur;
+        cur = dst;
+        std::swap(dcur, dprev);
+    }
+    return AWE_OK;
+}
+
 awe_status Plan::adjoint(const float* resid, float* src_adj, float* grad_phys, hipStream_t s) {
     if (!model_set) return fail(AWE_ESTATE, "awe_set_model has not been called on this plan");
     if (g.nrec > 0 && !resid) return fail(AWE_EINVAL, "resid is NULL but nrec > 0");
@@ -606,7 +648,7 @@ awe_status Plan::adjoint(const float* resid, float* src_adj, float* grad_phys, h
         const bool img = usnap != nullptr;
         StepArgs a{m1, m2, m2, coef, d_ez, d_ey, d_ex, usnap, img ? grad : nullptr};
         const LaunchShape& sh = img ? img_shape : fwd_shape;
-        AWE_HIP(launch_step(L, k, a, img, sh.cfg, sh.zchunk, s));
+        AWE_HIP(launch_step(L, k, a, img ? kStepImaging : kStepPlain, sh.cfg, sh.zchunk, s));
         if (g.nrec > 0)
             AWE_HIP(launch_inject(m2, coef, rec_csr.node, rec_csr.rowptr, rec_csr.pt, rec_csr.w, rec_csr.nrows,
                                   resid + (size_t)n * g.nrec, 1.f, usnap, img ? grad : nullptr, s));

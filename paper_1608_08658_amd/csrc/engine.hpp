@@ -80,6 +80,7 @@ struct awe_plan_s {
     std::vector<float*> slots;      // recompute buffers of one segment
     float *mu0 = nullptr, *mu1 = nullptr, *grad = nullptr;
     float* wavelet_copy = nullptr;
+    float *b_t = nullptr, *b_du0 = nullptr, *b_du1 = nullptr, *b_dm = nullptr;   // linearised modelling
     bool have_ckpt = false, have_grad = false;
 
     ~awe_plan_s();
@@ -88,6 +89,7 @@ struct awe_plan_s {
     awe_status forward(const float* wavelet, float* traces, int K, hipStream_t s);
     awe_status step(int n0, int nsteps, const float* wavelet, float* traces, hipStream_t s);
     awe_status adjoint(const float* resid, float* src_adj, float* grad_phys, hipStream_t s);
+    awe_status born(const float* wavelet, const float* dm_phys, float* traces, hipStream_t s);
 
     awe_status alloc(void** p, size_t bytes);
     awe_status alloc_field(float** p);

@@ -19,6 +19,7 @@ inline unsigned blocks_for(int64_t n, int64_t cap = 65535 * 8) {
 // deterministic and no atomics are needed.
 //   field[node] += C[node] * scale * sum_e w_e values[pt_e]
 //   imaging:  grad[node] += usnap[node] * (that same increment)
+//   save-t:   grad[node] += (that same increment)        (usnap == NULL)
 __global__ void __launch_bounds__(kBlock)
 inject_k(float* field, const float* coef, const int64_t* node, const int32_t* rowptr, const int32_t* pt,
          const float* w, int32_t nrows, const float* values, float scale, const float* usnap, float* grad) {
@@ -29,7 +30,7 @@ inject_k(float* field, const float* coef, const int64_t* node, const int32_t* ro
     const int64_t i = node[j];
     const float inc = coef[i] * (s * scale);
     field[i] += inc;
-    if (grad) grad[i] += usnap[i] * inc;
+    if (grad) grad[i] += (usnap ? usnap[i] : 1.f) * inc;   // imaging (u * inc) or save-t (inc)
 }
 
 // Receiver interpolation: out[r] = scale * sum_k w[r][k] field[node[r][k]].
@@ -132,6 +133,21 @@ pack_k(float* dense, const float* pitched, PadGeo g, float scale) {
         const int64_t y = (i / g.n2) % g.n1;
         const int64_t z = i / (g.n2 * g.n1);
         dense[i] = scale * pitched[g.origin + z * g.sz + y * g.sy + x];
+    }
+}
+
+// Edge-replication padding of a physical field onto the pitched padded grid.
+__global__ void __launch_bounds__(kBlock)
+pad_k(float* out, const float* m, PadGeo g) {
+    const int64_t total = g.n0 * g.n1 * g.n2;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (int64_t)gridDim.x * kBlock) {
+        const int64_t x = i % g.n2;
+        const int64_t y = (i / g.n2) % g.n1;
+        const int64_t z = i / (g.n2 * g.n1);
+        const int64_t pz = clampi(z - g.nbl, 0, g.p0 - 1);
+        const int64_t py = g.p1 > 1 ? clampi(y - g.nbl, 0, g.p1 - 1) : 0;
+        const int64_t px = clampi(x - g.nbl, 0, g.p2 - 1);
+        out[g.origin + z * g.sz + y * g.sy + x] = m[(pz * g.p1 + py) * g.p2 + px];
     }
 }
 
@@ -238,6 +254,13 @@ hipError_t launch_fold(float* grad_phys, const float* g, const Layout& L, const 
 hipError_t launch_pack(float* dense, const float* pitched, const Layout& L, float scale, hipStream_t s) {
     PadGeo g = pad_geo(L, nullptr, 0);
     hipLaunchKernelGGL(pack_k, dim3(blocks_for(L.points(), 8192)), dim3(kBlock), 0, s, dense, pitched, g, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_pad(float* pitched, const float* m_phys, const Layout& L, const int64_t phys[3], int nbl,
+                      hipStream_t s) {
+    PadGeo g = pad_geo(L, phys, nbl);
+    hipLaunchKernelGGL(pad_k, dim3(blocks_for(L.points(), 8192)), dim3(kBlock), 0, s, pitched, m_phys, g);
     return hipGetLastError();
 }
 

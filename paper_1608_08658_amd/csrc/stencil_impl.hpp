@@ -1,0 +1,469 @@
+// One time step of the damped acoustic scheme (Sec. V.A, Eq. 1 with the
+// damping of Listing 1), forward or adjoint, optionally fused with the
+// zero-lag imaging condition of the adjoint-state gradient (Eq. 3).
+//
+//   t   = C * L_P(uc) + a * (up - uc),        a = (eta_z + eta_y + eta_x) * C / dt
+//   out = 2 uc - up + t                        (= (2-a) uc - (1-a) up + C L_P uc)
+//
+// Modes (template parameter MODE, see StepMode):
+//   plain    just the update above;
+//   imaging  grad += usnap * t            (t = mu[n] - 2 mu[n+1] + mu[n+2] without
+//                                           the receiver term, which the injection adds);
+//   save-t   grad = t                      (the background's second time difference
+//                                           for linearised modelling, cancellation-free);
+//   born     t -= (C / dt^2) * usnap * grad (usnap = dm, grad = the background's
+//                                           second time difference): the scattered
+//                                           field's source of linearised (Born) modelling.
+//
+// The adjoint of the scheme is the same update run backwards in time, so one
+// kernel serves both directions.  Accumulating t instead of the second time
+// difference of mu avoids the cancellation of three nearly equal FP32 values.
+//
+// Memory access plan (HBM-bound: 16 B per point forward, 28 B with imaging):
+//   * a workgroup owns a 64 (x, one wavefront wide) x TY (y) column of the grid
+//     and streams through a chunk of z planes;
+//   * each thread keeps its points' z-neighbourhood (2M+1 planes) in registers,
+//     so every value of uc is fetched from HBM once per z-chunk;
+//   * the current plane, with an M-wide x/y halo, is staged in LDS (double
+//     buffered, one barrier per plane) for the x and y derivatives; the halo
+//     cells are re-read from L2 / the Infinity Cache, not HBM;
+//   * the loads for plane z+1 are issued before the barrier of plane z so their
+//     latency hides behind the arithmetic of plane z;
+//   * each thread owns RY consecutive y rows, so y-neighbours inside its own
+//     rows come from registers.
+// 2-D uses the same scheme with a 64-point x row in LDS and no y axis.
+#pragma once
+
+#include <type_traits>
+#include <utility>
+
+#include "awe_internal.hpp"
+
+namespace awe {
+namespace {
+
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+// f(integral_constant<int, 0>) ... f(integral_constant<int, N-1>), unrolled.
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// s_waitcnt vmcnt(0) (gfx9 encoding: expcnt and lgkmcnt left at their maxima).
+// Used once after the queue is filled: with no load of the prologue still in
+// flight when the loop starts, the compiler's wait analysis does not carry
+// them into the loop, where they would force a full drain on every plane.
+__device__ __forceinline__ void drain_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+__device__ __forceinline__ void lds_barrier() {
+    // Orders the LDS writes of this plane before other waves read them.  Only
+    // LDS needs to be visible across the workgroup; outstanding global loads
+    // (the prefetch of the next plane) are left in flight.
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+struct Geo3 {
+    int32_t nz, ny, nx;
+    int64_t sy, sz, origin;
+    uint32_t gx, gy, ntiles;     // tile grid (x tiles, y tiles) and total tiles incl. z chunks
+    int64_t total;               // elements in each field's allocation
+};
+
+// Workgroups are dealt to the 8 XCDs round-robin by linear id, and each XCD
+// has its own L2.  Remap so that XCD k runs the contiguous logical range
+// [k*per, (k+1)*per) of tiles (x fastest, then y, then z chunk): tiles that
+// share halo rows and columns then run at the same time on the same L2.
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ bool xcd_tile(const Geo3& g, uint32_t& bx, uint32_t& by, uint32_t& bz) {
+    const uint32_t per = gridDim.x / kXcds;
+    const uint32_t lin = (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+    if (lin >= g.ntiles) return false;
+    bx = lin % g.gx;
+    by = (lin / g.gx) % g.gy;
+    bz = lin / (g.gx * g.gy);
+    return true;
+}
+
+// Raw buffer access.  A descriptor covers one workgroup's slab of a field;
+// an offset at or beyond its size reads 0 and drops a store, so lanes with
+// nothing to load or store are given kOob instead of a branch.  The z-plane
+// offset is wave-uniform and goes in the scalar offset.
+constexpr uint32_t kOob = 0xFFFFFFF0u;
+constexpr int kRsrcWord3 = 0x00020000;   // gfx9 family: 32-bit data format
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t slab_rsrc(const float* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), 0, (int)bytes, kRsrcWord3);
+}
+// Cache policy of the arrays that are touched once per step (u[n-1], C, the
+// output, and with imaging the snapshot and gradient): the wavefield planes
+// re-read as halos and z-queue warm-up keep the default policy.
+#ifndef AWE_CPOL_STREAM
+#define AWE_CPOL_STREAM 2   // NT: stream through L2 with early eviction
+#endif
+template <int CPOL = 0>
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, CPOL));
+}
+template <int CPOL = 0>
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, float v, uint32_t voff, uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, CPOL);
+}
+
+template <int M, int BY, int RY, int MODE>
+__global__ void __launch_bounds__(kTileX * BY)
+step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk) {
+    constexpr int TY = BY * RY;
+    // LDS row pitch of 128 dwords (two 64-dword units): every y-neighbour pair
+    // (y-k, y+k) is then one ds_read2st64 with immediate offsets, instead of
+    // an address computation per pair at 80-dword pitches
+    constexpr int LW = 128;
+    static_assert(kTileX + 2 * M <= LW, "halo wider than the LDS row");
+    constexpr int LH = TY + 2 * M;
+    constexpr int NQ = 2 * M + 1;
+    constexpr int NH = (2 * M + BY - 1) / BY;     // y-halo rows per thread row
+    __shared__ float lds[2][LH][LW];
+
+    uint32_t bx, by, bz;
+    if (!xcd_tile(g, bx, by, bz)) return;          // uniform over the workgroup
+    const int tx = threadIdx.x;
+    const int ty = threadIdx.y;
+    const int x = bx * kTileX + tx;
+    const int yb = by * TY;
+    const int y0 = yb + ty * RY;
+    const int z0 = bz * zchunk;
+    const int z1 = min(z0 + zchunk, g.nz);
+    if (z0 >= z1) return;
+
+    // slab base: grid point (z0 - M, -M, -M); every access of this workgroup
+    // lies at a non-negative offset from it and inside the allocation
+    const int64_t sy = g.sy, sz = g.sz;
+    const int64_t slab = g.origin + (int64_t)(z0 - M) * sz - (int64_t)M * sy - M;
+    const uint64_t left = (uint64_t)(g.total - slab) * 4u;
+    const uint32_t bytes = left > 0x7FFFFFF0ull ? 0x7FFFFFF0u : (uint32_t)left;
+    const auto r_uc = slab_rsrc(a.uc + slab, bytes);
+    const auto r_up = slab_rsrc(a.up + slab, bytes);
+    const auto r_out = slab_rsrc(a.out + slab, bytes);
+    const auto r_cf = slab_rsrc(a.coef + slab, bytes);
+    const auto r_us = slab_rsrc((MODE == kStepImaging || MODE == kStepBorn) ? a.usnap + slab : a.uc + slab, bytes);
+    const auto r_gr = slab_rsrc(MODE != kStepPlain ? a.grad + slab : a.out + slab, bytes);
+    const uint32_t plane = (uint32_t)(sz * 4);     // bytes per z plane
+    auto soff = [&](int z) { return (uint32_t)(z - z0 + M) * plane; };
+    auto voff = [&](int y, int xx) { return (uint32_t)(((int64_t)(y + M) * sy + xx + M) * 4); };
+
+    const bool xin = x < g.nx;                     // this lane owns a grid point
+    const bool xld = x < g.nx + M;                 // this lane's column is in the allocation
+    uint32_t o_in[RY], o_ld[RY];                   // per-row offsets for owned / loadable points
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        const uint32_t o = voff(y0 + r, x);
+        o_in[r] = (xin && y0 + r < g.ny) ? o : kOob;
+        o_ld[r] = (xld && y0 + r < g.ny + M) ? o : kOob;
+    }
+    // x halo: lanes tx < M load the left columns, lanes tx >= 64-M the right ones.
+    const bool hl = tx < M;
+    const bool hr = tx >= kTileX - M;
+    const int hx = hl ? ((int)bx * kTileX - M + tx) : ((int)bx * kTileX + M + tx);
+    const int hlx = hl ? tx : (tx + 2 * M);        // LDS column of the halo value
+    uint32_t o_hx[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r)
+        o_hx[r] = ((hl || hr) && hx < g.nx + M && y0 + r < g.ny + M) ? voff(y0 + r, hx) : kOob;
+    // y halo: 2M rows (M above, M below the tile), 64 columns; thread row ty
+    // loads halo rows h = ty, ty + BY, ... < 2M.
+    int hyrow[NH];
+    uint32_t o_hy[NH];
+#pragma unroll
+    for (int i = 0; i < NH; ++i) {
+        const int h = ty + i * BY;
+        const int y = (h < M) ? (yb - M + h) : (yb + TY + (h - M));
+        hyrow[i] = (h < M) ? h : (TY + h);
+        o_hy[i] = ((h < 2 * M) && xld && (y < g.ny + M)) ? voff(y, x) : kOob;
+    }
+
+    const float exv = xin ? a.eta_x[x] : 0.f;
+    float eyv[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) eyv[r] = (y0 + r < g.ny) ? a.eta_y[y0 + r] : 0.f;
+
+    // register queue of the z-neighbourhood: q[r][j] = uc(z - M + j)
+    float q[RY][NQ];
+#pragma unroll
+    for (int j = 1; j < NQ; ++j)
+#pragma unroll
+        for (int r = 0; r < RY; ++r) q[r][j] = bload(r_uc, o_ld[r], soff(z0 - M + j - 1));
+    drain_vmem();
+
+    float fr[RY], pv[RY], cv[RY], sv[RY], gv[RY], hxv[RY], hyv[NH], ezn;
+    auto fetch = [&](int z) {
+        // first in the batch: vector-memory counters retire in order, so the
+        // compute of plane z - 1 only waits for loads issued before this one
+        ezn = a.eta_z[z];
+        const uint32_t so = soff(z), sf = soff(z + M);
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            fr[r] = bload(r_uc, o_ld[r], sf);
+            pv[r] = bload<AWE_CPOL_STREAM>(r_up, o_in[r], so);
+            cv[r] = bload<AWE_CPOL_STREAM>(r_cf, o_in[r], so);
+            if (MODE == kStepImaging || MODE == kStepBorn) {
+                sv[r] = bload<AWE_CPOL_STREAM>(r_us, o_in[r], so);
+                gv[r] = bload<AWE_CPOL_STREAM>(r_gr, o_in[r], so);
+            }
+            hxv[r] = bload(r_uc, o_hx[r], so);
+        }
+#pragma unroll
+        for (int i = 0; i < NH; ++i) hyv[i] = bload(r_uc, o_hy[i], so);
+    };
+    fetch(z0);
+
+    // One plane.  The z-queue is never shifted: in iteration z the logical
+    // slot j (plane z - M + j) lives in physical slot (j + PH) % NQ, with PH
+    // advancing by one per plane.  The loop is unrolled NQ times so PH is a
+    // compile-time constant and no register moves are needed.
+    auto one_plane = [&](auto ph, int z) {
+        constexpr int PH = decltype(ph)::value;
+        auto Q = [&](int r, int j) -> float& { return q[r][(j + PH) % NQ]; };
+        const int b = (z - z0) & 1;
+#pragma unroll
+        for (int r = 0; r < RY; ++r) Q(r, NQ - 1) = fr[r];
+        // stage plane z in LDS
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            lds[b][M + ty * RY + r][M + tx] = Q(r, M);
+            if (hl || hr) lds[b][M + ty * RY + r][hlx] = hxv[r];
+        }
+#pragma unroll
+        for (int i = 0; i < NH; ++i)
+            if (ty + i * BY < 2 * M) lds[b][hyrow[i]][M + tx] = hyv[i];
+
+        float p[RY], c[RY], s[RY], gg[RY];
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            p[r] = pv[r];
+            c[r] = cv[r];
+            if (MODE == kStepImaging || MODE == kStepBorn) { s[r] = sv[r]; gg[r] = gv[r]; }
+        }
+        const float ezv = ezn;
+        if (z + 1 < z1) fetch(z + 1);
+        lds_barrier();
+
+        const uint32_t so = soff(z);
+        // One LDS offset per thread and one per row, hidden from the optimiser
+        // (the empty asm emits nothing): every neighbour is then an immediate
+        // offset from them (x: 0..2M dwords, y: multiples of LW), so each pair
+        // of reads is one ds_read2 / ds_read2st64 with no address arithmetic.
+        int lofs = (b * LH + ty * RY) * LW + tx + M;   // (row ly - M, column lx)
+        asm volatile("" : "+v"(lofs));
+        int lrow[RY];                                  // (row ly, column lx - M)
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            lrow[r] = lofs + (r + M) * LW - M;
+            asm volatile("" : "+v"(lrow[r]));
+        }
+        const float* lflat = &lds[0][0][0];
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            const float* ly = lflat + lofs + (r + M) * LW;   // this point, y pairs
+            const float* lx = lflat + lrow[r] + M;           // this point, x pairs
+            float lap = k.c0 * Q(r, M);
+#pragma unroll
+            for (int kk = 1; kk <= M; ++kk) {
+                const float yu = (r - kk >= 0) ? Q((r - kk) >= 0 ? (r - kk) : 0, M) : ly[-kk * LW];
+                const float yd = (r + kk < RY) ? Q((r + kk) < RY ? (r + kk) : 0, M) : ly[kk * LW];
+                lap += k.cz[kk] * (Q(r, M - kk) + Q(r, M + kk));
+                lap += k.cy[kk] * (yu + yd);
+                lap += k.cx[kk] * (lx[-kk] + lx[kk]);
+            }
+            const float u0 = Q(r, M);
+            const float av = (ezv + eyv[r] + exv) * c[r] * k.inv_dt;
+            float t = c[r] * lap + av * (p[r] - u0);
+            if (MODE == kStepBorn) t -= (c[r] * k.inv_dt2) * (s[r] * gg[r]);
+            bstore<AWE_CPOL_STREAM>(r_out, (u0 - p[r]) + u0 + t, o_in[r], so);
+            if (MODE == kStepImaging) bstore<AWE_CPOL_STREAM>(r_gr, gg[r] + s[r] * t, o_in[r], so);
+            if (MODE == kStepSaveT) bstore<AWE_CPOL_STREAM>(r_gr, t, o_in[r], so);
+        }
+    };
+    // before plane z0 the queue holds planes z0-M .. z0+M-1 in physical slots
+    // 1..NQ-1, i.e. logical slot j sits in (j + 1) % NQ: the first plane has PH = 1
+    int z = z0;
+    for (;;) {
+        static_for<NQ>([&](auto s_) {
+            constexpr int PH = (decltype(s_)::value + 1) % NQ;
+            if (z < z1) one_plane(std::integral_constant<int, PH>{}, z);
+            ++z;
+        });
+        if (z >= z1) break;
+    }
+}
+
+struct Geo2 {
+    int32_t nz, nx;
+    int64_t sz, origin, total;
+};
+
+// 2-D: block = 64 x NW threads; wave w streams z planes [zw, zw + zchunk).
+template <int M, int NW, int MODE>
+__global__ void __launch_bounds__(kTileX * NW)
+step2d(StepArgs a, StencilCoef k, Geo2 g, int zchunk) {
+    constexpr int LW = kTileX + 2 * M;
+    constexpr int NQ = 2 * M + 1;
+    __shared__ float lds[2][NW][LW];
+
+    const int tx = threadIdx.x;
+    const int w = threadIdx.y;
+    const int x = blockIdx.x * kTileX + tx;
+    const int zw = (blockIdx.y * NW + w) * zchunk;        // first plane of this wave
+    const int zend = min(zw + zchunk, g.nz);              // <= zw for an idle wave
+    const bool live_wave = zw < g.nz;
+
+    // slab base: grid point (zw - M, -M); an idle wave gets an empty slab
+    const int64_t sz = g.sz;
+    const int64_t slab = live_wave ? g.origin + (int64_t)(zw - M) * sz - M : 0;
+    const uint64_t left = live_wave ? (uint64_t)(g.total - slab) * 4u : 0;
+    const uint32_t bytes = left > 0x7FFFFFF0ull ? 0x7FFFFFF0u : (uint32_t)left;
+    const auto r_uc = slab_rsrc(a.uc + slab, bytes);
+    const auto r_up = slab_rsrc(a.up + slab, bytes);
+    const auto r_out = slab_rsrc(a.out + slab, bytes);
+    const auto r_cf = slab_rsrc(a.coef + slab, bytes);
+    const auto r_us = slab_rsrc((MODE == kStepImaging || MODE == kStepBorn) ? a.usnap + slab : a.uc + slab, bytes);
+    const auto r_gr = slab_rsrc(MODE != kStepPlain ? a.grad + slab : a.out + slab, bytes);
+    const uint32_t plane = (uint32_t)(sz * 4);
+    auto soff = [&](int z) { return (uint32_t)(z - zw + M) * plane; };
+
+    const bool xin = x < g.nx;
+    const bool xld = x < g.nx + M;
+    const uint32_t o_in = xin ? (uint32_t)(x + M) * 4u : kOob;
+    const uint32_t o_ld = xld ? (uint32_t)(x + M) * 4u : kOob;
+    const bool hl = tx < M;
+    const bool hr = tx >= kTileX - M;
+    const int hx = hl ? ((int)blockIdx.x * kTileX - M + tx) : ((int)blockIdx.x * kTileX + M + tx);
+    const int hlx = hl ? tx : (tx + 2 * M);
+    const uint32_t o_hx = ((hl || hr) && hx < g.nx + M) ? (uint32_t)(hx + M) * 4u : kOob;
+    const float exv = xin ? a.eta_x[x] : 0.f;
+
+    float q[NQ];
+#pragma unroll
+    for (int j = 1; j < NQ; ++j) q[j] = bload(r_uc, o_ld, soff(zw - M + j - 1));
+    drain_vmem();
+    float fr, pv, cv, sv = 0.f, gv = 0.f, hv, ezn;
+    auto fetch = [&](int z) {
+        const bool live = z < zend;                   // wave-uniform
+        ezn = live ? a.eta_z[z] : 0.f;                // first in the batch (in-order counters)
+        const uint32_t so = soff(z);
+        fr = bload(r_uc, live ? o_ld : kOob, soff(z + M));
+        pv = bload<AWE_CPOL_STREAM>(r_up, live ? o_in : kOob, so);
+        cv = bload<AWE_CPOL_STREAM>(r_cf, live ? o_in : kOob, so);
+        if (MODE == kStepImaging || MODE == kStepBorn) {
+            sv = bload<AWE_CPOL_STREAM>(r_us, live ? o_in : kOob, so);
+            gv = bload<AWE_CPOL_STREAM>(r_gr, live ? o_in : kOob, so);
+        }
+        hv = bload(r_uc, live ? o_hx : kOob, so);
+    };
+    fetch(zw);
+    for (int i = 0; i < zchunk; ++i) {
+        const int z = zw + i;
+        const int b = i & 1;
+#pragma unroll
+        for (int j = 0; j < NQ - 1; ++j) q[j] = q[j + 1];
+        q[NQ - 1] = fr;
+        lds[b][w][M + tx] = q[M];
+        if (hl || hr) lds[b][w][hlx] = hv;
+        const float p = pv, c = cv, s = sv, gg = gv, ezv = ezn;
+        if (i + 1 < zchunk) fetch(z + 1);
+        lds_barrier();
+        if (z < zend) {
+            const int lx = M + tx;
+            float lap = k.c0 * q[M];
+#pragma unroll
+            for (int kk = 1; kk <= M; ++kk) {
+                lap += k.cz[kk] * (q[M - kk] + q[M + kk]);
+                lap += k.cx[kk] * (lds[b][w][lx - kk] + lds[b][w][lx + kk]);
+            }
+            const float u0 = q[M];
+            const float av = (ezv + exv) * c * k.inv_dt;
+            float t = c * lap + av * (p - u0);
+            if (MODE == kStepBorn) t -= (c * k.inv_dt2) * (s * gg);
+            bstore<AWE_CPOL_STREAM>(r_out, (u0 - p) + u0 + t, o_in, soff(z));
+            if (MODE == kStepImaging) bstore<AWE_CPOL_STREAM>(r_gr, gg + s * t, o_in, soff(z));
+            if (MODE == kStepSaveT) bstore<AWE_CPOL_STREAM>(r_gr, t, o_in, soff(z));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launch-shape tables
+// 3-D configurations: (BY, RY) -> workgroup 64 x BY threads, tile 64 x BY*RY.
+// 2-D configurations: NW waves per workgroup.
+// ---------------------------------------------------------------------------
+template <int M, int MODE>
+hipError_t launch3(int cfg, const Layout& L, const StencilCoef& k, const StepArgs& a, int zchunk, hipStream_t s) {
+    const int ty = tile_rows(3, cfg);
+    Geo3 g{(int32_t)L.n[0], (int32_t)L.n[1], (int32_t)L.n[2], L.sy, L.sz, L.origin, 0, 0, 0, L.total};
+    g.gx = (uint32_t)((L.n[2] + kTileX - 1) / kTileX);
+    g.gy = (uint32_t)((L.n[1] + ty - 1) / ty);
+    const uint32_t gz = (uint32_t)((L.n[0] + zchunk - 1) / zchunk);
+    g.ntiles = g.gx * g.gy * gz;
+    const dim3 grid((g.ntiles + kXcds - 1) / kXcds * kXcds);   // a multiple of the XCD count
+    if constexpr (MODE == kStepBorn || MODE == kStepSaveT) {
+        // linearised modelling uses one shape (cfg 3) to bound the number of kernels
+        if (cfg != 3) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((step3d<M, 8, 2, MODE>), grid, dim3(kTileX, 8), 0, s, a, k, g, zchunk);
+        return hipGetLastError();
+    } else {
+        switch (cfg) {
+            case 0:     // 64 x 16 tile, 256 threads, 4 rows per thread
+                hipLaunchKernelGGL((step3d<M, 4, 4, MODE>), grid, dim3(kTileX, 4), 0, s, a, k, g, zchunk);
+                break;
+            case 1:     // 64 x 8 tile, 256 threads, 2 rows per thread
+                hipLaunchKernelGGL((step3d<M, 4, 2, MODE>), grid, dim3(kTileX, 4), 0, s, a, k, g, zchunk);
+                break;
+            case 2:     // 64 x 32 tile, 512 threads, 4 rows per thread
+                hipLaunchKernelGGL((step3d<M, 8, 4, MODE>), grid, dim3(kTileX, 8), 0, s, a, k, g, zchunk);
+                break;
+            default:    // 64 x 16 tile, 512 threads, 2 rows per thread
+                hipLaunchKernelGGL((step3d<M, 8, 2, MODE>), grid, dim3(kTileX, 8), 0, s, a, k, g, zchunk);
+                break;
+        }
+        return hipGetLastError();
+    }
+}
+
+template <int M, int MODE>
+hipError_t launch2(int cfg, const Layout& L, const StencilCoef& k, const StepArgs& a, int zchunk, hipStream_t s) {
+    Geo2 g{(int32_t)L.n[0], (int32_t)L.n[2], L.sz, L.origin, L.total};
+    const unsigned gx = (unsigned)((L.n[2] + kTileX - 1) / kTileX);
+    const int nw = (cfg == 0) ? 4 : 1;
+    const int64_t per_block = (int64_t)nw * zchunk;
+    dim3 grid(gx, (unsigned)((L.n[0] + per_block - 1) / per_block));
+    if constexpr (MODE == kStepBorn || MODE == kStepSaveT) {
+        if (cfg != 0) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((step2d<M, 4, MODE>), grid, dim3(kTileX, 4), 0, s, a, k, g, zchunk);
+    } else {
+        if (nw == 4)
+            hipLaunchKernelGGL((step2d<M, 4, MODE>), grid, dim3(kTileX, 4), 0, s, a, k, g, zchunk);
+        else
+            hipLaunchKernelGGL((step2d<M, 1, MODE>), grid, dim3(kTileX, 1), 0, s, a, k, g, zchunk);
+    }
+    return hipGetLastError();
+}
+
+// every mode for one half-width M
+template <int M>
+hipError_t launch_m(const Layout& L, const StencilCoef& k, const StepArgs& a, int mode, int cfg, int zchunk,
+                    hipStream_t s) {
+    const bool d3 = L.ndim == 3;
+    switch (mode) {
+        case kStepPlain: return d3 ? launch3<M, kStepPlain>(cfg, L, k, a, zchunk, s) : launch2<M, kStepPlain>(cfg, L, k, a, zchunk, s);
+        case kStepImaging: return d3 ? launch3<M, kStepImaging>(cfg, L, k, a, zchunk, s) : launch2<M, kStepImaging>(cfg, L, k, a, zchunk, s);
+        case kStepBorn: return d3 ? launch3<M, kStepBorn>(cfg, L, k, a, zchunk, s) : launch2<M, kStepBorn>(cfg, L, k, a, zchunk, s);
+        case kStepSaveT: return d3 ? launch3<M, kStepSaveT>(cfg, L, k, a, zchunk, s) : launch2<M, kStepSaveT>(cfg, L, k, a, zchunk, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+}  // namespace awe

@@ -20,7 +20,7 @@ import numpy as np
 __all__ = [
     "ricker", "ricker_fn", "layered_velocity", "gaussian_anomaly", "smooth",
     "Shot", "config_2d_small", "config_3d_forward", "config_3d_gradient",
-    "config_3d_gradient_crop", "config_served_gradient", "serving_requests",
+    "config_3d_gradient_crop", "config_served_gradient", "config_paper_example", "serving_requests",
     "random_traces", "random_state",
 ]
 
@@ -228,6 +228,23 @@ def config_served_gradient(seed: int = 5, n: int = 300, nbl: int = 40, nt: int =
                           10.0, damp_vref=float(min(vt.min(), v0.min())),
                           extra={"m_true": 1.0 / vt ** 2, "checkpoint_every": 30}))
     return shots
+
+
+def config_paper_example(seed: int = 6, t_end: float = 1.0) -> Shot:
+    """The paper's own 3-D modelling run (Sec. V.D): 201 x 201 x 70 points
+    (70 in depth) with a 40-point layer on every side (281 x 281 x 150
+    computed), h = 15 m, 10 Hz Ricker, 1 s modelled, space order 14.  The paper
+    gives no velocity model; a seeded layered model (1.5-4.5 km/s) stands in.
+    201 receivers on a line across the centre at depth 2h.  ``nt`` is set from
+    the modelled time once dt is known (see ``extra['t_end']``)."""
+    rng = np.random.default_rng(seed)
+    shape = (70, 201, 201)
+    h = 15.0
+    v = layered_velocity(shape, rng)
+    src = np.array([[2.5 * h, 100.3 * h, 100.6 * h]])
+    rec = np.stack([np.full(201, 2.0 * h), np.full(201, 100.0 * h), np.arange(201) * h], axis=1)
+    return Shot("paper-3d-201x201x70-o14", shape, (h, h, h), 14, 40, 0, 1.0 / v ** 2, src, rec, 10.0,
+                damp_vref=float(v.min()), extra={"t_end": t_end})
 
 
 def serving_requests(seed: int, count: int, scale: float = 1.0) -> list[Shot]:

@@ -43,7 +43,7 @@ def test_2d_orders(order):
     assert e_tr <= TOL and e_u <= TOL
 
 
-@pytest.mark.parametrize("order", [2, 4, 6, 8, 12, 16])
+@pytest.mark.parametrize("order", [2, 4, 6, 8, 10, 12, 14, 16])
 def test_3d_orders_multi_tile_ragged(order):
     shot = small_3d_shot(200 + order, order)
     log(f"case {shot.name} shape {shot.shape} nbl {shot.nbl}")

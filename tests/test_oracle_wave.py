@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 import synth
+import oracle
 from oracle import Operator, Problem, dt_max, misfit, weights_f64
 from oracle.analytic import greens_2d, greens_3d
 
@@ -200,3 +201,28 @@ def test_zero_wavelet_gives_zero_traces_and_first_sample_is_zero():
     assert np.all(op.forward(np.zeros((p.nt, 2)))["traces"] == 0.0)
     tr = op.forward(synth.ricker(25.0, p.dt, p.nt)[:, None].repeat(2, 1))["traces"]
     assert np.all(tr[0] == 0.0) and np.any(tr[5] != 0.0)
+
+
+def test_born_is_the_derivative_of_the_forward():
+    # J dm against a central difference of the forward map (FP64).
+    p, m, w, d_obs, dm = _grad_setup(41)
+    op = Operator(p, m)
+    jdm = op.born(w, dm)
+    eps = 1e-4
+    fp = Operator(p, m + eps * dm).forward(w)["traces"]
+    fm = Operator(p, m - eps * dm).forward(w)["traces"]
+    fd = (fp - fm) / (2 * eps)
+    assert np.linalg.norm(jdm - fd) <= 1e-7 * np.linalg.norm(fd)
+
+
+def test_born_dot_product_with_the_gradient():
+    # <J dm, y> = <dm, J^T y>, J^T y being the adjoint-state gradient driven by y.
+    p, m, w, d_obs, dm = _grad_setup(43)
+    op = Operator(p, m)
+    rng = np.random.default_rng(2)
+    y = synth.random_traces(rng, p.nt, len(p.rec_coords), 25.0, p.dt)
+    fwd = op.forward(w, keep=True)
+    jty = oracle.fold_padding(op.adjoint(y, history=fwd["history"])["grad_pad"], p.nbl)
+    lhs = np.sum(op.born(w, dm) * y)
+    rhs = np.sum(dm * jty)
+    assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), abs(rhs))
