@@ -285,6 +285,7 @@ def main():
     ap.add_argument("--gradient-n", type=int, default=400,
                     help="physical points per axis of the gradient workload (0 = skip it)")
     ap.add_argument("--gradient-nt", type=int, default=2000, help="time samples of the gradient workload")
+    ap.add_argument("--paper-example", type=int, default=1, help="run the paper's 3-D example workload (0 = skip)")
     ap.add_argument("--serve-requests", type=int, default=64, help="requests in the serving run (0 = skip)")
     ap.add_argument("--serve-scale", type=float, default=0.5, help="size/step scale of the serving mix")
     ap.add_argument("--served-gradient-shots", type=int, default=0,
@@ -370,8 +371,10 @@ def main():
         log("gradient workload ...")
         grad = bench_gradient(torch, awe, synth, n=args.gradient_n, nt=args.gradient_nt)
 
-    log("paper example workload ...")
-    paper = bench_paper_example(torch, awe, synth)
+    paper = None
+    if args.paper_example:
+        log("paper example workload ...")
+        paper = bench_paper_example(torch, awe, synth)
 
     serve = None
     if args.serve_requests > 0:
