@@ -1,0 +1,177 @@
+"""Edge cases and error paths on the GPU: degenerate step counts, no sources
+or receivers, points on the last grid plane or inside the absorbing layer,
+co-located receivers, the smallest grids, and invalid models."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import dev, gpu_plan, host, log, oracle_problem, rel_l2, shot_dt, small_2d_shot, small_3d_shot
+
+pytestmark = pytest.mark.gpu
+
+
+def _both(shot, dt, w, y=None, K=None):
+    op = oracle.Operator(oracle_problem(shot, dt), shot.m)
+    plan = gpu_plan(shot, dt)
+    plan.set_model(dev(shot.m))
+    import torch
+    wt = dev(w) if w is not None and w.size else None
+    tr = plan.forward(wt, ckpt_every=K or 0)
+    out = {"tr": host(tr)}
+    ref = {"tr": op.forward(w if w is not None else np.zeros((shot.nt, 0)))["traces"]}
+    if y is not None:
+        src_adj, g = plan.adjoint(dev(y), want_src_adj=len(shot.src_coords) > 0, want_grad=K is not None)
+        out["src_adj"] = host(src_adj) if src_adj is not None else None
+        out["g"] = host(g) if g is not None else None
+        if K is not None:
+            fwd = op.forward(w, keep=True)
+            adj = op.adjoint(y, history=fwd["history"])
+            ref["g"] = oracle.fold_padding(adj["grad_pad"], shot.nbl)
+        else:
+            adj = op.adjoint(y)
+        ref["src_adj"] = adj["src_adj"]
+    plan.close()
+    return out, ref
+
+
+@pytest.mark.parametrize("nt", [1, 2, 3])
+def test_tiny_step_counts(nt):
+    shot = small_3d_shot(900 + nt, 4, nt=nt)
+    dt = shot_dt(shot)
+    w = shot.wavelet(dt).astype(np.float32) * 1e3
+    rng = np.random.default_rng(nt)
+    y = rng.standard_normal((nt, len(shot.rec_coords))).astype(np.float32)
+    out, ref = _both(shot, dt, w, y=y, K=1)
+    assert np.all(out["tr"][0] == 0.0)
+    assert np.allclose(out["tr"], ref["tr"], rtol=1e-4, atol=1e-6 * max(1.0, np.abs(ref["tr"]).max()))
+    assert np.all(out["src_adj"][-1] == 0.0)
+    assert np.allclose(out["src_adj"], ref["src_adj"], rtol=1e-4, atol=1e-6 * max(1e-30, np.abs(ref["src_adj"]).max()))
+    if nt == 1:
+        assert np.all(out["g"] == 0.0)
+    else:
+        assert rel_l2(out["g"], ref["g"]) <= 1e-4
+
+
+def test_no_sources_gives_zero_traces_and_no_receivers_gives_empty():
+    shot = small_2d_shot(910, 4, nt=50)
+    shot.src_coords = np.zeros((0, 2))
+    dt = shot_dt(shot)
+    plan = gpu_plan(shot, dt)
+    plan.set_model(dev(shot.m))
+    tr = host(plan.forward(None))
+    assert np.all(tr == 0.0)
+    plan.close()
+    shot2 = small_2d_shot(911, 4, nt=50)
+    shot2.rec_coords = np.zeros((0, 2))
+    plan = gpu_plan(shot2, dt)
+    plan.set_model(dev(shot2.m))
+    tr = plan.forward(dev(shot2.wavelet(dt)), ckpt_every=10)
+    assert tuple(tr.shape) == (50, 0)
+    import torch
+    src_adj, g = plan.adjoint(torch.zeros((50, 0), device="cuda"), want_src_adj=True, want_grad=True)
+    assert np.all(host(src_adj) == 0.0) and np.all(host(g) == 0.0)
+    plan.close()
+
+
+def test_points_on_last_plane_in_the_layer_and_colocated():
+    # receivers on the far edge of the padded grid (the last plane), inside
+    # the absorbing layer, at the exact origin, and several at one position
+    shot = small_3d_shot(920, 8, nt=70)
+    P = [(n - 1 + shot.nbl) * h for n, h in zip(shot.shape, shot.spacing)]
+    lo = [-shot.nbl * h for h in shot.spacing]
+    rec = np.array([P, lo, [0.0, 0.0, 0.0], [P[0], 0.0, lo[2]], [33.3, 44.4, 55.5], [33.3, 44.4, 55.5],
+                    [33.3, 44.4, 55.5], [-2.5 * shot.spacing[0], 200.0, P[2] - 1.0]])
+    shot.rec_coords = rec
+    shot.src_coords = np.array([[lo[0] + 0.5 * shot.spacing[0], 100.0, 120.0]])   # source inside the layer
+    dt = shot_dt(shot)
+    w = shot.wavelet(dt).astype(np.float32)
+    rng = np.random.default_rng(1)
+    y = rng.standard_normal((shot.nt, len(rec))).astype(np.float32)
+    out, ref = _both(shot, dt, w, y=y, K=9)
+    scale = np.abs(ref["tr"]).max()
+    assert np.max(np.abs(out["tr"] - ref["tr"])) <= 1e-4 * scale
+    assert np.array_equal(out["tr"][:, 4], out["tr"][:, 5]) and np.array_equal(out["tr"][:, 4], out["tr"][:, 6])
+    assert rel_l2(out["src_adj"], ref["src_adj"]) <= 1e-4
+    assert rel_l2(out["g"], ref["g"]) <= 1e-4
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_smallest_grids_order2_no_layer(ndim):
+    shape = (2,) * ndim
+    h = (10.0,) * ndim
+    m = np.full(shape, 1.0 / 2000.0 ** 2)
+    shot = synth.Shot("tiny", shape, h, 2, 0, 40, m, np.array([[5.0] * ndim]), np.array([[3.0] * ndim]), 30.0)
+    dt = shot_dt(shot)
+    w = shot.wavelet(dt).astype(np.float32)
+    out, ref = _both(shot, dt, w)
+    assert rel_l2(out["tr"], ref["tr"]) <= 1e-4
+
+
+def test_invalid_models_and_calls_are_errors():
+    import torch
+    import paper_1608_08658_amd as awe
+    shot = small_2d_shot(930, 4, nt=20)
+    dt = shot_dt(shot)
+    plan = gpu_plan(shot, dt)
+    bad = shot.m.copy()
+    bad[3, 4] = np.nan
+    with pytest.raises(awe.AweError) as e:
+        plan.set_model(dev(bad))
+    assert e.value.status == -5
+    with pytest.raises(awe.AweError) as e:
+        plan.set_model(dev(-shot.m))
+    assert e.value.status == -5
+    with pytest.raises(awe.AweError) as e:           # dt above the stability limit of a faster model
+        plan.set_model(dev(shot.m / 9.0))
+    assert e.value.status == -5
+    with pytest.raises(awe.AweError) as e:           # no model yet
+        plan.forward(dev(shot.wavelet(dt)))
+    assert e.value.status == -4
+    plan.set_model(dev(shot.m))
+    plan.forward(dev(shot.wavelet(dt)))
+    with pytest.raises(awe.AweError) as e:
+        plan.step(0, shot.nt)                         # beyond nt - 1 steps
+    assert e.value.status == -1
+    plan.close()
+    with pytest.raises(awe.AweError) as e:
+        gpu_plan(shot, dt, rec=[[-1e6, 0.0]])         # receiver far outside the grid
+    assert e.value.status == -1
+
+
+def test_full_size_order16_state_steps_sampled():
+    # The 480^3 order-16 grid of the gradient workload in its launch shape:
+    # two steps from a seeded smooth random state, sampled against the oracle
+    # evaluated on sub-blocks (corners, faces, the layer, tile seams).
+    shot = synth.config_3d_gradient(nt=3, nrec_side=4)
+    dt = shot_dt(shot)
+    rng = np.random.default_rng(43)
+    P = tuple(n + 2 * shot.nbl for n in shot.shape)
+    log(f"case order-16 full-size state steps {P}")
+    u0 = synth.random_state(rng, P, 4.0).astype(np.float32)
+    um = (0.999 * u0).astype(np.float32)
+    plan = gpu_plan(shot, dt)
+    plan.set_model(dev(shot.m))
+    plan.set_state(dev(u0), dev(um))
+    nsteps = 2
+    plan.step(0, nsteps)
+    u, _ = plan.get_state()
+    u = host(u)
+    plan.close()
+    op = oracle.Operator(oracle_problem(shot, dt, nt=nsteps + 1), shot.m)
+    from oracle.fd import laplacian
+    r = nsteps * shot.order // 2
+    pts = [(0, 0, 0), (P[0] - 1, P[1] - 1, P[2] - 1), (69, 15, 63), (70, 16, 64), (240, 240, 240),
+           (479, 0, 128), (140, 479, 1), (300, 31, 447)]
+    for p in pts:
+        lo = [max(0, p[a] - r) for a in range(3)]
+        hi = [min(P[a], p[a] + r + 1) for a in range(3)]
+        sl = tuple(slice(lo[a], hi[a]) for a in range(3))
+        cu, cp = u0[sl].astype(np.float64), um[sl].astype(np.float64)
+        for _ in range(nsteps):
+            nxt = op.A[sl] * cu - op.B[sl] * cp + op.C[sl] * laplacian(cu, shot.spacing, shot.order)
+            cp, cu = cu, nxt
+        want = cu[tuple(p[a] - lo[a] for a in range(3))]
+        got = u[p]
+        log(f"  point {p}: gpu {got:.7e} oracle {want:.7e}")
+        assert abs(got - want) <= 1e-5 * max(abs(want), 1e-3 * np.max(np.abs(u0))), p
