@@ -115,6 +115,26 @@ awe_status awe_dt_max(int32_t ndim, int32_t order, const double* spacing_host, d
 awe_status awe_footprint(const awe_geometry* g, int32_t ckpt_every, uint64_t* bytes);
 
 /*
+ * Binomial checkpointing (Griewank 1992; Griewank & Walther 2000, the
+ * "revolve" schedule): the alternative to a stored full history of the
+ * forward wavefield that the paper names as under evaluation (Sec. IV.B.4).
+ * The gradient's reverse sweep (Eqs. 3-4) visits the states
+ * (u[t], u[t-1]), t = nt-1 .. 0; with `snapshots` stored states the schedule
+ * takes the fewest forward steps that any schedule with that many stored
+ * states can.  For nt time samples, *forward_steps_host receives the forward
+ * steps of the whole gradient (the first sweep's nt - 1 included) and
+ * *fields_host the wavefield buffers the schedule holds at most (a stored
+ * state is a pair of fields; states one step apart share one).  nt >= 1,
+ * snapshots >= 0; schedules above 2^31 forward steps are AWE_EINVAL.
+ * Pure host function.
+ */
+awe_status awe_binomial_cost(int32_t nt, int32_t snapshots, int64_t* forward_steps_host, int32_t* fields_host);
+
+/* Device bytes a plan for `g` holds for forward + gradient with binomial
+ * checkpointing over `snapshots` stored states.  Pure host function. */
+awe_status awe_footprint_binomial(const awe_geometry* g, int32_t snapshots, uint64_t* bytes);
+
+/*
  * Validate `g`, build the off-grid point tables and allocate the plan's
  * forward fields on the current HIP device.  Coordinates outside the padded
  * grid are AWE_EINVAL.  The plan owns every device buffer it allocates;
@@ -154,6 +174,19 @@ awe_status awe_forward(awe_plan plan, const float* wavelet_dev, float* traces_de
                        int32_t ckpt_every, awe_stream stream);
 
 /*
+ * awe_forward (same traces, bit for bit) storing the states of the binomial
+ * schedule with `snapshots` stored states (awe_binomial_cost) instead of
+ * periodic checkpoints, for one following awe_adjoint with a gradient, which
+ * runs the rest of the schedule and consumes it: a second gradient needs a
+ * new call (AWE_ESTATE otherwise).  Stored states reference the forward's
+ * own buffers, so nothing is copied.  The gradient equals that of the
+ * periodic checkpoints bit for bit.  The final state stays in the plan until
+ * that gradient runs.
+ */
+awe_status awe_forward_binomial(awe_plan plan, const float* wavelet_dev, float* traces_dev,
+                                int32_t snapshots, awe_stream stream);
+
+/*
  * Adjoint modelling (Eq. 4, Listing 2) driven by receiver data resid_dev
  * [nt][nrec], run backwards in time:
  *   mu[n] = (2-a) mu[n+1] - (1-a) mu[n+2] + C (L mu[n+1] + R^T y[n]),
@@ -163,8 +196,9 @@ awe_status awe_forward(awe_plan plan, const float* wavelet_dev, float* traces_de
  * 1/2 ||traces - d_obs||^2 with respect to the physical m when resid_dev =
  * traces - d_obs (Eq. 3, the exact derivative of the discrete misfit);
  * it needs the preceding awe_forward on this plan to have used
- * ckpt_every > 0 (else AWE_ESTATE).  Segments are recomputed from the
- * checkpoints during the sweep.
+ * ckpt_every > 0, or an awe_forward_binomial not yet used by a gradient
+ * (else AWE_ESTATE).  Forward states are recomputed from the stored ones
+ * during the sweep.
  */
 awe_status awe_adjoint(awe_plan plan, const float* resid_dev, float* src_adj_dev,
                        float* grad_m_dev, awe_stream stream);

@@ -41,11 +41,14 @@ _SIGNATURES = {
     "awe_fd_weights": (_I32, [_I32, C.POINTER(_D)]),
     "awe_dt_max": (_I32, [_I32, _I32, C.POINTER(_D), _D, C.POINTER(_D)]),
     "awe_footprint": (_I32, [C.POINTER(Geometry), _I32, C.POINTER(_U64)]),
+    "awe_binomial_cost": (_I32, [_I32, _I32, C.POINTER(_I64), C.POINTER(_I32)]),
+    "awe_footprint_binomial": (_I32, [C.POINTER(Geometry), _I32, C.POINTER(_U64)]),
     "awe_plan_create": (_I32, [C.POINTER(Geometry), C.POINTER(_P)]),
     "awe_plan_destroy": (_I32, [_P]),
     "awe_plan_info": (_I32, [_P, C.POINTER(_I64)]),
     "awe_set_model": (_I32, [_P, _P, _P]),
     "awe_forward": (_I32, [_P, _P, _P, _I32, _P]),
+    "awe_forward_binomial": (_I32, [_P, _P, _P, _I32, _P]),
     "awe_adjoint": (_I32, [_P, _P, _P, _P, _P]),
     "awe_born": (_I32, [_P, _P, _P, _P, _P]),
     "awe_get_gradient_padded": (_I32, [_P, _P, _P]),

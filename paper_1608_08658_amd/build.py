@@ -21,7 +21,7 @@ OUT = os.path.join(HERE, "libawe.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
 SOURCES = ["kernels_stencil_hi.hip", "kernels_stencil_lo.hip", "kernels_stencil.hip", "kernels_aux.hip",
-           "engine.cpp", "api.cpp", "server.cpp"]
+           "engine.cpp", "checkpoint.cpp", "api.cpp", "server.cpp"]
 
 ARCH = "gfx950"
 FLAGS = [

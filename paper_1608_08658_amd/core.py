@@ -92,10 +92,24 @@ def dt_max(ndim: int, order: int, spacing, vmax: float) -> float:
     return out.value
 
 
-def footprint(geom: GeometryHolder, ckpt_every: int = 0) -> int:
+def footprint(geom: GeometryHolder, ckpt_every: int = 0, snapshots: int | None = None) -> int:
+    """Device bytes of a plan: forward only, periodic checkpoints every
+    ``ckpt_every`` steps, or (``snapshots`` given) binomial checkpointing."""
     out = C.c_uint64()
-    check(lib().awe_footprint(C.byref(geom.g), int(ckpt_every), C.byref(out)))
+    if snapshots is not None:
+        check(lib().awe_footprint_binomial(C.byref(geom.g), int(snapshots), C.byref(out)))
+    else:
+        check(lib().awe_footprint(C.byref(geom.g), int(ckpt_every), C.byref(out)))
     return out.value
+
+
+def binomial_cost(nt: int, snapshots: int) -> tuple[int, int]:
+    """(forward steps of a whole gradient, wavefield buffers held) for the
+    binomial checkpointing schedule over nt samples with ``snapshots``
+    stored states."""
+    steps, fields = C.c_int64(), C.c_int32()
+    check(lib().awe_binomial_cost(int(nt), int(snapshots), C.byref(steps), C.byref(fields)))
+    return steps.value, fields.value
 
 
 def misfit(traces, d_obs, want_resid=True):
@@ -150,12 +164,19 @@ class Plan:
     def set_model(self, m):
         check(lib().awe_set_model(self.handle, _ptr(m, "m", self.shape), _stream()))
 
-    def forward(self, wavelet, ckpt_every=0, traces=None):
+    def forward(self, wavelet, ckpt_every=0, traces=None, snapshots=None):
+        """Traces of a forward run; ``ckpt_every`` > 0 keeps periodic
+        checkpoints, ``snapshots`` (not None) the states of the binomial
+        schedule, for a following gradient."""
         torch = _torch()
         if traces is None:
             traces = torch.empty((self.nt, self.nrec), dtype=torch.float32, device="cuda")
-        check(lib().awe_forward(self.handle, _ptr(wavelet, "wavelet", (self.nt, self.nsrc), allow_none=self.nsrc == 0),
-                                _ptr(traces, "traces", (self.nt, self.nrec)), int(ckpt_every), _stream()))
+        w = _ptr(wavelet, "wavelet", (self.nt, self.nsrc), allow_none=self.nsrc == 0)
+        tr = _ptr(traces, "traces", (self.nt, self.nrec))
+        if snapshots is not None:
+            check(lib().awe_forward_binomial(self.handle, w, tr, int(snapshots), _stream()))
+        else:
+            check(lib().awe_forward(self.handle, w, tr, int(ckpt_every), _stream()))
         return traces
 
     def adjoint(self, resid, want_src_adj=True, want_grad=False):
@@ -204,14 +225,18 @@ def _make_gradient_fn():
 
     class Gradient(torch.autograd.Function):
         """traces = F(m, wavelet) on a plan; backward gives dL/dm (physical
-        model, adjoint-state with checkpoints every ``ckpt_every`` steps) and
-        dL/dwavelet (F^T applied to dL/dtraces)."""
+        model, adjoint-state with checkpoints every ``ckpt_every`` steps, or
+        with binomial checkpointing over ``snapshots`` stored states when
+        that is given) and dL/dwavelet (F^T applied to dL/dtraces)."""
 
         @staticmethod
-        def forward(ctx, m, wavelet, plan, ckpt_every=30):
+        def forward(ctx, m, wavelet, plan, ckpt_every=30, snapshots=None):
             plan.set_model(m.contiguous())
             need_m = ctx.needs_input_grad[0]
-            traces = plan.forward(wavelet.contiguous(), ckpt_every=ckpt_every if need_m else 0)
+            if need_m and snapshots is not None:
+                traces = plan.forward(wavelet.contiguous(), snapshots=snapshots)
+            else:
+                traces = plan.forward(wavelet.contiguous(), ckpt_every=ckpt_every if need_m else 0)
             ctx.plan = plan
             return traces
 
@@ -220,7 +245,7 @@ def _make_gradient_fn():
             plan = ctx.plan
             src_adj, grad = plan.adjoint(grad_traces.contiguous(), want_src_adj=ctx.needs_input_grad[1],
                                          want_grad=ctx.needs_input_grad[0])
-            return grad, src_adj, None, None
+            return grad, src_adj, None, None, None
 
     return Gradient
 

@@ -60,6 +60,33 @@ awe_status awe_footprint(const awe_geometry* g, int32_t ckpt_every, uint64_t* by
     return AWE_OK;
 }
 
+awe_status awe_binomial_cost(int32_t nt, int32_t snapshots, int64_t* forward_steps, int32_t* fields) {
+    if (!forward_steps || !fields) return fail(AWE_EINVAL, "output pointer is NULL");
+    if (nt < 1) return fail(AWE_EINVAL, "nt must be >= 1");
+    if (snapshots < 0) return fail(AWE_EINVAL, "snapshots must be >= 0");
+    AWE_TRY({
+        awe::Reversal r;
+        awe_status st = awe::binomial_prepare(r, nt, snapshots);
+        if (st) return st;
+        *forward_steps = r.steps;
+        *fields = r.pool;
+    });
+    return AWE_OK;
+}
+
+awe_status awe_footprint_binomial(const awe_geometry* g, int32_t snapshots, uint64_t* bytes) {
+    awe_status st = awe::validate(g);
+    if (st) return st;
+    if (!bytes) return fail(AWE_EINVAL, "output pointer is NULL");
+    if (snapshots < 0) return fail(AWE_EINVAL, "snapshots must be >= 0");
+    AWE_TRY({
+        awe::Reversal r;
+        if ((st = awe::binomial_prepare(r, g->nt, snapshots))) return st;
+        *bytes = awe::footprint_binomial_bytes(g, r.pool);
+    });
+    return AWE_OK;
+}
+
 awe_status awe_plan_create(const awe_geometry* g, awe_plan* out) {
     if (!out) return fail(AWE_EINVAL, "output pointer is NULL");
     *out = nullptr;
@@ -109,6 +136,12 @@ awe_status awe_set_model(awe_plan plan, const float* m, awe_stream s) {
 awe_status awe_forward(awe_plan plan, const float* wavelet, float* traces, int32_t ckpt_every, awe_stream s) {
     if (!plan) return fail(AWE_EINVAL, "plan is NULL");
     AWE_TRY(return plan->forward(wavelet, traces, ckpt_every, as_stream(s)));
+}
+
+awe_status awe_forward_binomial(awe_plan plan, const float* wavelet, float* traces, int32_t snapshots,
+                                awe_stream s) {
+    if (!plan) return fail(AWE_EINVAL, "plan is NULL");
+    AWE_TRY(return plan->forward_binomial(wavelet, traces, snapshots, as_stream(s)));
 }
 
 awe_status awe_adjoint(awe_plan plan, const float* resid, float* src_adj, float* grad_m, awe_stream s) {

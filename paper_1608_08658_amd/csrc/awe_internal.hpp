@@ -65,11 +65,31 @@ hipError_t launch_step(const Layout& L, const StencilCoef& k, const StepArgs& a,
 int num_tile_cfgs(int ndim);
 int tile_rows(int ndim, int tile_cfg);   // y rows (3-D) or z chunks per block (2-D)
 
-hipError_t launch_inject(float* field, const float* coef, const int64_t* node, const int32_t* rowptr,
-                         const int32_t* pt, const float* w, int32_t nrows, const float* values, float scale,
-                         const float* usnap, float* grad, hipStream_t s);
-hipError_t launch_sample(float* out, const float* field, const int64_t* node, const float* w, int32_t npts,
-                         int32_t corners, float scale, hipStream_t s);
+// One launch of the off-grid point operators (kernels_aux.hip): injection
+// into one array and sampling of another.  A zero count disables either part.
+struct InjectOp {
+    float* field = nullptr;              // receives the injection
+    const float* coef = nullptr;         // C on the padded grid
+    const int64_t* node = nullptr;       // CSR by grid node: node index per row
+    const int32_t* rowptr = nullptr;     // nrows + 1 row starts
+    const int32_t* pt = nullptr;         // point index per entry
+    const float* w = nullptr;            // multilinear weight per entry
+    const float* values = nullptr;       // one value per point (this time step)
+    const float* usnap = nullptr;        // imaging: forward wavefield u[n]
+    float* grad = nullptr;               // imaging / save-t accumulator (or NULL)
+    float scale = 1.f;
+    int32_t nrows = 0;
+};
+struct SampleOp {
+    float* out = nullptr;                // npts values
+    const float* field = nullptr;        // sampled array
+    const int64_t* node = nullptr;       // [npts][corners] grid nodes
+    const float* w = nullptr;            // [npts][corners] weights
+    float scale = 1.f;
+    int32_t npts = 0;
+    int32_t corners = 0;
+};
+hipError_t launch_sparse(const InjectOp& a, const SampleOp& b, hipStream_t s);
 hipError_t launch_coef(float* coef, const float* m_phys, const Layout& L, const int64_t phys[3], int nbl,
                        const double* eta_z, const double* eta_y, const double* eta_x, double dt, hipStream_t s);
 hipError_t launch_minmax(const float* m, int64_t n, float* partial /* [3 * blocks] */, int blocks, hipStream_t s);

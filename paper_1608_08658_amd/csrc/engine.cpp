@@ -158,6 +158,14 @@ uint64_t footprint_bytes(const awe_geometry* g, int K) {
     return b;
 }
 
+uint64_t footprint_binomial_bytes(const awe_geometry* g, int pool_fields) {
+    int64_t pad[3], phys[3];
+    padded_zyx(g, pad, phys);
+    const Layout L = make_layout(g->ndim, pad, g->space_order / 2);
+    const uint64_t field = (uint64_t)L.total * 4;
+    return footprint_bytes(g, 0) + (uint64_t)(pool_fields + 3) * field + (uint64_t)g->nt * g->nsrc * 4;
+}
+
 // ---------------------------------------------------------------------------
 // damping tables and off-grid point tables
 // ---------------------------------------------------------------------------
@@ -257,7 +265,7 @@ awe_status Plan::alloc(void** p, size_t bytes) {
         *p = nullptr;
         return fail(AWE_ENOMEM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
     }
-    owned.push_back(*p);
+    owned.push_back({*p, bytes});
     held += bytes;
     return AWE_OK;
 }
@@ -280,13 +288,15 @@ awe_status Plan::upload(T** dst, const std::vector<T>& v) {
 
 void Plan::release(void* p) {
     if (!p) return;
-    auto it = std::find(owned.begin(), owned.end(), p);
-    if (it != owned.end()) owned.erase(it);
+    auto it = std::find_if(owned.begin(), owned.end(), [p](const std::pair<void*, size_t>& o) { return o.first == p; });
+    if (it == owned.end()) return;   // not the plan's
+    held -= it->second;
+    owned.erase(it);
     (void)hipFree(p);
 }
 
 Plan::~awe_plan_s() {
-    for (void* p : owned) (void)hipFree(p);
+    for (auto& o : owned) (void)hipFree(o.first);
 }
 
 awe_status Plan::init(const awe_geometry* geo) {
@@ -487,24 +497,78 @@ awe_status Plan::set_model(const float* m, hipStream_t s) {
     return AWE_OK;
 }
 
-// One step of the recurrence from (uc, up) into out, then the point source.
-awe_status Plan::advance(const float* uc, const float* up, float* out, const float* q_row, hipStream_t s) {
+// Injection of the source row q_row into field (none if q_row is NULL).
+InjectOp Plan::src_op(float* field, const float* q_row, float* t_acc) const {
+    InjectOp a;
+    if (!q_row || g.nsrc == 0) return a;
+    a.field = field;
+    a.coef = coef;
+    a.node = src_csr.node;
+    a.rowptr = src_csr.rowptr;
+    a.pt = src_csr.pt;
+    a.w = src_csr.w;
+    a.values = q_row;
+    a.grad = t_acc;
+    a.scale = (float)(1.0 / vol);
+    a.nrows = src_csr.nrows;
+    return a;
+}
+
+// Receiver sampling of field into row (none if row is NULL).
+SampleOp Plan::rec_op(float* row, const float* field) const {
+    SampleOp b;
+    if (!row || g.nrec == 0) return b;
+    b.out = row;
+    b.field = field;
+    b.node = rec_node;
+    b.w = rec_w;
+    b.npts = g.nrec;
+    b.corners = corners;
+    return b;
+}
+
+// One step of the recurrence from (uc, up) into out, then one launch that
+// injects the point source into out and, if rec_row is given, records the
+// receivers' samples of uc (the previous step's result, left untouched by
+// this step) into rec_row.
+awe_status Plan::advance(const float* uc, const float* up, float* out, const float* q_row, float* rec_row,
+                         hipStream_t s) {
     StepArgs a{uc, up, out, coef, d_ez, d_ey, d_ex, nullptr, nullptr};
     AWE_HIP(launch_step(L, k, a, kStepPlain, fwd_shape.cfg, fwd_shape.zchunk, s));
-    if (q_row && g.nsrc > 0)
-        AWE_HIP(launch_inject(out, coef, src_csr.node, src_csr.rowptr, src_csr.pt, src_csr.w, src_csr.nrows, q_row,
-                              (float)(1.0 / vol), nullptr, nullptr, s));
+    AWE_HIP(launch_sparse(src_op(out, q_row, nullptr), rec_op(rec_row, uc), s));
     return AWE_OK;
 }
 
-awe_status Plan::ensure_gradient_storage(int K) {
-    if (K == ckpt_K && storage_ready) return AWE_OK;
-    storage_ready = false;
-    // (re)allocate for a new K
+void Plan::release_periodic() {
     for (auto& kv : stored) release(kv.second);
     stored.clear();
     for (float* p : slots) release(p);
     slots.clear();
+    ckpt_K = 0;
+    storage_ready = false;
+}
+
+void Plan::release_binomial() {
+    for (float* p : rev_pool) release(p);
+    rev_pool.clear();
+    rev_snaps = -1;
+}
+
+// Adjoint fields (mu pair, imaging accumulator) and the wavelet copy the
+// reverse sweep's recomputation injects.
+awe_status Plan::ensure_adjoint_storage() {
+    awe_status st;
+    if (!mu0 && ((st = alloc_field(&mu0)) || (st = alloc_field(&mu1)))) return st;
+    if (!grad && (st = alloc_field(&grad))) return st;
+    if (!wavelet_copy && g.nsrc > 0 && (st = alloc((void**)&wavelet_copy, (size_t)g.nt * g.nsrc * sizeof(float))))
+        return st;
+    return AWE_OK;
+}
+
+awe_status Plan::ensure_gradient_storage(int K) {
+    release_binomial();
+    if (K == ckpt_K && storage_ready) return AWE_OK;
+    release_periodic();
     awe_status st;
     for (int t : stored_times(g.nt, K)) {
         float* p = nullptr;
@@ -516,12 +580,28 @@ awe_status Plan::ensure_gradient_storage(int K) {
         if ((st = alloc_field(&p))) return st;
         slots.push_back(p);
     }
-    if (!mu0 && ((st = alloc_field(&mu0)) || (st = alloc_field(&mu1)) || (st = alloc_field(&grad)))) return st;
-    if (!wavelet_copy && g.nsrc > 0 && (st = alloc((void**)&wavelet_copy, (size_t)g.nt * g.nsrc * sizeof(float))))
-        return st;
+    if ((st = ensure_adjoint_storage())) return st;
     ckpt_K = K;
     AWE_HIP(hipDeviceSynchronize());
     storage_ready = true;
+    return AWE_OK;
+}
+
+awe_status Plan::ensure_binomial_storage(int snapshots) {
+    release_periodic();
+    awe_status st;
+    if (rev_snaps != snapshots) {
+        release_binomial();
+        if ((st = binomial_prepare(rev, g.nt, snapshots))) return st;
+        rev_snaps = snapshots;
+    }
+    while ((int)rev_pool.size() < rev.pool) {
+        float* p = nullptr;
+        if ((st = alloc_field(&p))) return st;
+        rev_pool.push_back(p);
+    }
+    if ((st = ensure_adjoint_storage())) return st;
+    AWE_HIP(hipDeviceSynchronize());
     return AWE_OK;
 }
 
@@ -539,9 +619,11 @@ awe_status Plan::forward(const float* wavelet, float* traces, int K, hipStream_t
     }
     AWE_HIP(launch_fill(w0, L.total, 0.f, s));
     AWE_HIP(launch_fill(w1, L.total, 0.f, s));
-    if (traces && g.nrec > 0) AWE_HIP(launch_fill(traces, g.nrec, 0.f, s));
     cur = w0;
     prev = w1;
+    // Trace row n is recorded in the launch that injects into u[n+1]; row 0
+    // samples u[0] = 0 and the last row follows the loop.
+    float* const tr = (traces && g.nrec > 0) ? traces : nullptr;
     for (int n = 0; n + 1 < g.nt; ++n) {
         float* dst = nullptr;
         if (K > 0) {
@@ -549,13 +631,49 @@ awe_status Plan::forward(const float* wavelet, float* traces, int K, hipStream_t
             if (it != stored.end()) dst = it->second;
         }
         if (!dst) dst = pick_work_dst();
-        if ((st = advance(cur, prev, dst, g.nsrc ? wavelet + (size_t)n * g.nsrc : nullptr, s))) return st;
-        if (traces && g.nrec > 0)
-            AWE_HIP(launch_sample(traces + (size_t)(n + 1) * g.nrec, dst, rec_node, rec_w, g.nrec, corners, 1.f, s));
+        if ((st = advance(cur, prev, dst, g.nsrc ? wavelet + (size_t)n * g.nsrc : nullptr,
+                          tr ? tr + (size_t)n * g.nrec : nullptr, s)))
+            return st;
         prev = cur;
         cur = dst;
     }
+    if (tr) AWE_HIP(launch_sparse(InjectOp{}, rec_op(tr + (size_t)(g.nt - 1) * g.nrec, cur), s));
     have_ckpt = K > 0;
+    rev_mode = false;
+    return AWE_OK;
+}
+
+// The forward sweep of a binomial checkpointing schedule (checkpoint.cpp):
+// the schedule's first descent is the plain forward from x_0 to x_(nt-1),
+// storing its snapshots as it passes them.  The executor stops before the
+// first visit; awe_adjoint runs the rest.
+awe_status Plan::forward_binomial(const float* wavelet, float* traces, int snapshots, hipStream_t s) {
+    if (!model_set) return fail(AWE_ESTATE, "awe_set_model has not been called on this plan");
+    if (g.nsrc > 0 && !wavelet) return fail(AWE_EINVAL, "wavelet is NULL but nsrc > 0");
+    if (snapshots < 0) return fail(AWE_EINVAL, "snapshots must be >= 0");
+    have_ckpt = false;
+    awe_status st;
+    if ((st = ensure_binomial_storage(snapshots))) return st;
+    if (g.nsrc > 0)
+        AWE_HIP(hipMemcpyAsync(wavelet_copy, wavelet, (size_t)g.nt * g.nsrc * sizeof(float), hipMemcpyDeviceToDevice, s));
+    AWE_HIP(launch_fill(w0, L.total, 0.f, s));   // x_0 = (0, 0)
+    rev.rewind();
+    float* const tr = (traces && g.nrec > 0) ? traces : nullptr;
+    auto buf = [&](int b) { return b < 0 ? w0 : rev_pool[b]; };
+    st = rev.run(
+        true,
+        [&](int n, int uc, int up, int out) {
+            return advance(buf(uc), buf(up), buf(out), g.nsrc ? wavelet + (size_t)n * g.nsrc : nullptr,
+                           tr ? tr + (size_t)n * g.nrec : nullptr, s);
+        },
+        [](int, int) { return AWE_OK; });
+    if (st) return st;
+    if (rev.t != g.nt - 1) return fail(AWE_EINVAL, "checkpoint schedule: forward sweep ended at %d", rev.t);
+    if (tr) AWE_HIP(launch_sparse(InjectOp{}, rec_op(tr + (size_t)(g.nt - 1) * g.nrec, buf(rev.ua)), s));
+    cur = buf(rev.ua);
+    prev = buf(rev.ub);
+    have_ckpt = true;
+    rev_mode = true;
     return AWE_OK;
 }
 
@@ -569,14 +687,19 @@ awe_status Plan::step(int n0, int nsteps, const float* wavelet, float* traces, h
     if (n0 < 0 || nsteps < 0 || (int64_t)n0 + nsteps > (int64_t)g.nt - 1)
         return fail(AWE_EINVAL, "steps %d..%d exceed nt-1 = %d", n0, n0 + nsteps, g.nt - 1);
     awe_status st;
+    // Row n+1 receives the sample of u[n+1]: recorded by the next step's
+    // injection launch, the last one after the loop.  Row n0 is not written.
+    float* const tr = (traces && g.nrec > 0) ? traces : nullptr;
     for (int n = n0; n < n0 + nsteps; ++n) {
         float* dst = pick_work_dst();
-        if ((st = advance(cur, prev, dst, (wavelet && g.nsrc) ? wavelet + (size_t)n * g.nsrc : nullptr, s))) return st;
-        if (traces && g.nrec > 0)
-            AWE_HIP(launch_sample(traces + (size_t)(n + 1) * g.nrec, dst, rec_node, rec_w, g.nrec, corners, 1.f, s));
+        if ((st = advance(cur, prev, dst, (wavelet && g.nsrc) ? wavelet + (size_t)n * g.nsrc : nullptr,
+                          (tr && n > n0) ? tr + (size_t)n * g.nrec : nullptr, s)))
+            return st;
         prev = cur;
         cur = dst;
     }
+    if (tr && nsteps > 0)
+        AWE_HIP(launch_sparse(InjectOp{}, rec_op(tr + (size_t)(n0 + nsteps) * g.nrec, cur), s));
     return AWE_OK;
 }
 
@@ -595,7 +718,7 @@ awe_status Plan::born(const float* wavelet, const float* dm_phys, float* traces,
         return st;
     AWE_HIP(launch_pad(b_dm, dm_phys, L, phys, g.nbl, s));
     for (float* f : {w0, w1, b_du0, b_du1}) AWE_HIP(launch_fill(f, L.total, 0.f, s));
-    if (traces && g.nrec > 0) AWE_HIP(launch_fill(traces, g.nrec, 0.f, s));
+    float* const tr = (traces && g.nrec > 0) ? traces : nullptr;
     have_ckpt = false;
     cur = w0;
     prev = w1;
@@ -607,17 +730,16 @@ awe_status Plan::born(const float* wavelet, const float* dm_phys, float* traces,
         float* dst = const_cast<float*>(prev);          // in place over u[n-1]
         StepArgs a{cur, prev, dst, coef, d_ez, d_ey, d_ex, nullptr, b_t};
         AWE_HIP(launch_step(L, k, a, kStepSaveT, cfg, zc, s));
-        if (g.nsrc > 0)
-            AWE_HIP(launch_inject(dst, coef, src_csr.node, src_csr.rowptr, src_csr.pt, src_csr.w, src_csr.nrows,
-                                  wavelet + (size_t)n * g.nsrc, (float)(1.0 / vol), nullptr, b_t, s));
+        // the source into u[n+1] (and t); trace row n samples du[n]
+        AWE_HIP(launch_sparse(src_op(dst, g.nsrc ? wavelet + (size_t)n * g.nsrc : nullptr, b_t),
+                              rec_op(tr ? tr + (size_t)n * g.nrec : nullptr, dcur), s));
         StepArgs b{dcur, dprev, dprev, coef, d_ez, d_ey, d_ex, b_dm, b_t};
         AWE_HIP(launch_step(L, k, b, kStepBorn, cfg, zc, s));
-        if (traces && g.nrec > 0)
-            AWE_HIP(launch_sample(traces + (size_t)(n + 1) * g.nrec, dprev, rec_node, rec_w, g.nrec, corners, 1.f, s));
         prev = cur;
         cur = dst;
         std::swap(dcur, dprev);
     }
+    if (tr) AWE_HIP(launch_sparse(InjectOp{}, rec_op(tr + (size_t)(g.nt - 1) * g.nrec, dcur), s));
     return AWE_OK;
 }
 
@@ -630,6 +752,8 @@ awe_status Plan::adjoint(const float* resid, float* src_adj, float* grad_phys, h
     awe_status st;
     if (!mu0 && ((st = alloc_field(&mu0)) || (st = alloc_field(&mu1)))) return st;
     if (want_grad && !grad && (st = alloc_field(&grad))) return st;
+    if (want_grad && rev_mode && rev.pos >= rev.sched.size())
+        return fail(AWE_ESTATE, "the binomial checkpoints were used by an earlier gradient; run awe_forward_binomial again");
     if (want_grad && !img_tuned) {
         if ((st = tune(true, s))) return st;
         img_tuned = true;
@@ -642,16 +766,38 @@ awe_status Plan::adjoint(const float* resid, float* src_adj, float* grad_phys, h
     float* m2 = mu1;   // mu[n+2]
     const float inv_vol = (float)(1.0 / vol);
 
+    // mu[n] from (mu[n+1], mu[n+2]) in place over mu[n+2], then one launch
+    // that injects the residual row n into mu[n] and samples mu[n+1] (left
+    // untouched) at the sources into row n of the adjoint source.
     auto adj_step = [&](int n, const float* usnap) -> awe_status {
-        if (src_adj && g.nsrc > 0 && n <= g.nt - 2)
-            AWE_HIP(launch_sample(src_adj + (size_t)n * g.nsrc, m1, src_node, src_w, g.nsrc, corners, inv_vol, s));
         const bool img = usnap != nullptr;
         StepArgs a{m1, m2, m2, coef, d_ez, d_ey, d_ex, usnap, img ? grad : nullptr};
         const LaunchShape& sh = img ? img_shape : fwd_shape;
         AWE_HIP(launch_step(L, k, a, img ? kStepImaging : kStepPlain, sh.cfg, sh.zchunk, s));
-        if (g.nrec > 0)
-            AWE_HIP(launch_inject(m2, coef, rec_csr.node, rec_csr.rowptr, rec_csr.pt, rec_csr.w, rec_csr.nrows,
-                                  resid + (size_t)n * g.nrec, 1.f, usnap, img ? grad : nullptr, s));
+        InjectOp inj;
+        if (g.nrec > 0) {
+            inj.field = m2;
+            inj.coef = coef;
+            inj.node = rec_csr.node;
+            inj.rowptr = rec_csr.rowptr;
+            inj.pt = rec_csr.pt;
+            inj.w = rec_csr.w;
+            inj.values = resid + (size_t)n * g.nrec;
+            inj.usnap = usnap;
+            inj.grad = img ? grad : nullptr;
+            inj.nrows = rec_csr.nrows;
+        }
+        SampleOp smp;
+        if (src_adj && g.nsrc > 0 && n <= g.nt - 2) {
+            smp.out = src_adj + (size_t)n * g.nsrc;
+            smp.field = m1;
+            smp.node = src_node;
+            smp.w = src_w;
+            smp.scale = inv_vol;
+            smp.npts = g.nsrc;
+            smp.corners = corners;
+        }
+        AWE_HIP(launch_sparse(inj, smp, s));
         std::swap(m1, m2);
         return AWE_OK;
     };
@@ -663,12 +809,31 @@ awe_status Plan::adjoint(const float* resid, float* src_adj, float* grad_phys, h
         return AWE_OK;
     }
 
-    // Reverse sweep over segments [jK, min(jK+K, nt) - 1], j = S-1 .. 0.
-    const int K = ckpt_K;
-    const int S = (g.nt + K - 1) / K;
     float* zero = w0;                         // u[0] = u[-1] = 0
     AWE_HIP(launch_fill(zero, L.total, 0.f, s));
     const float* qsrc = g.nsrc ? wavelet_copy : nullptr;
+
+    if (rev_mode) {
+        // The rest of the binomial schedule: recompute forward steps from
+        // stored states and visit t = nt-1 .. 0 with the adjoint step.
+        auto buf = [&](int b) { return b < 0 ? zero : rev_pool[b]; };
+        st = rev.run(
+            false,
+            [&](int n, int uc, int up, int out) {
+                return advance(buf(uc), buf(up), buf(out), qsrc ? qsrc + (size_t)n * g.nsrc : nullptr, nullptr, s);
+            },
+            [&](int t, int uc) { return adj_step(t, t >= 1 ? buf(uc) : nullptr); });
+        if (st) return st;
+        AWE_HIP(launch_fold(grad_phys, grad, L, phys, g.nbl, (float)(-1.0 / (g.dt * g.dt)), s));
+        cur = prev = zero;   // the wavefield state no longer holds u[nt-1]
+        have_ckpt = false;
+        have_grad = true;
+        return AWE_OK;
+    }
+
+    // Reverse sweep over segments [jK, min(jK+K, nt) - 1], j = S-1 .. 0.
+    const int K = ckpt_K;
+    const int S = (g.nt + K - 1) / K;
     std::vector<const float*> ptr;            // ptr[t - (t0 - 1)] = u[t]
     for (int j = S - 1; j >= 0; --j) {
         const int t0 = j * K;
@@ -686,7 +851,7 @@ awe_status Plan::adjoint(const float* resid, float* src_adj, float* grad_phys, h
         for (int t = t0 + 1; t <= t1; ++t) {
             if (at(t)) continue;
             float* dst = slots[slot++];
-            if ((st = advance(at(t - 1), at(t - 2), dst, qsrc ? qsrc + (size_t)(t - 1) * g.nsrc : nullptr, s)))
+            if ((st = advance(at(t - 1), at(t - 2), dst, qsrc ? qsrc + (size_t)(t - 1) * g.nsrc : nullptr, nullptr, s)))
                 return st;
             at(t) = dst;
         }

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "awe.h"
@@ -39,6 +40,119 @@ struct DeviceCsr {
     int32_t nrows = 0;
 };
 
+// Binomial checkpointing (checkpoint.cpp).
+struct CkptAction {
+    enum Kind : int32_t { kAdvance = 0, kTake = 1, kRestore = 2, kFree = 3, kYield = 4 };
+    int32_t kind;
+    int32_t arg;   // advance / yield: a time index; take / restore / free: a snapshot (-1 = x_0 = 0)
+};
+int64_t binomial_steps(int64_t nstates, int free_snapshots);
+std::vector<CkptAction> binomial_schedule(int nt, int snapshots);
+class Reversal;
+awe_status binomial_prepare(Reversal& r, int nt, int snapshots);   // schedule, pool size, step count
+uint64_t footprint_binomial_bytes(const awe_geometry* g, int pool_fields);
+
+class Reversal {
+public:
+    std::vector<CkptAction> sched;
+    size_t pos = 0;          // next action
+    int pool = 0;            // wavefield buffers the schedule needs
+    bool sized = false;
+    int64_t steps = 0;       // forward steps taken since rewind()
+    int visited = 0;         // states visited since rewind()
+    int ua = -1, ub = -1;    // current state (u[t], u[t-1]) as buffer indices; -1 = the zero field
+    int t = 0;
+    int nt = 0;
+
+    awe_status init(int nt, int snapshots);
+    void rewind();
+    // Runs actions from `pos`.  step(n, uc, up, out) computes u[n+1] from
+    // u[n] (buffer uc) and u[n-1] (up) into out; visit(t, uc) is the visit
+    // of state t.  With stop_at_visit the run stops before the first visit.
+    template <class Step, class Visit>
+    awe_status run(bool stop_at_visit, Step&& step, Visit&& visit) {
+        return run_impl(stop_at_visit, false, step, visit);
+    }
+
+private:
+    struct Snap {
+        int ua = -1, ub = -1, t = -1;
+    };
+    std::vector<Snap> snaps;
+    std::vector<int> ref;
+    int take_buffer(bool grow);
+    void hold(int b) { if (b >= 0) ++ref[b]; }
+    void drop(int b) { if (b >= 0) --ref[b]; }
+    template <class Step, class Visit>
+    awe_status run_impl(bool stop_at_visit, bool grow, Step&& step, Visit&& visit);
+};
+
+template <class Step, class Visit>
+awe_status Reversal::run_impl(bool stop_at_visit, bool grow, Step&& step, Visit&& visit) {
+    for (; pos < sched.size(); ++pos) {
+        const CkptAction a = sched[pos];
+        switch (a.kind) {
+        case CkptAction::kAdvance:
+            if (a.arg <= t) return fail(AWE_EINVAL, "checkpoint schedule: advance to %d from %d", a.arg, t);
+            while (t < a.arg) {
+                const int out = take_buffer(grow);
+                if (out < -1) return fail(AWE_EINVAL, "checkpoint schedule: no free buffer at step %d", t);
+                awe_status st = step(t, ua, ub, out);
+                if (st) return st;
+                hold(out);
+                drop(ub);
+                ub = ua;
+                ua = out;
+                ++t;
+                ++steps;
+            }
+            break;
+        case CkptAction::kTake:
+            if (a.arg < 0 || a.arg >= (int)snaps.size() || snaps[a.arg].t >= 0)
+                return fail(AWE_EINVAL, "checkpoint schedule: bad snapshot %d", a.arg);
+            snaps[a.arg] = Snap{ua, ub, t};
+            hold(ua);
+            hold(ub);
+            break;
+        case CkptAction::kRestore: {
+            Snap s{-1, -1, 0};
+            if (a.arg >= 0) {
+                if (a.arg >= (int)snaps.size() || snaps[a.arg].t < 0)
+                    return fail(AWE_EINVAL, "checkpoint schedule: restore of empty snapshot %d", a.arg);
+                s = snaps[a.arg];
+            }
+            hold(s.ua);
+            hold(s.ub);
+            drop(ua);
+            drop(ub);
+            ua = s.ua;
+            ub = s.ub;
+            t = s.t;
+            break;
+        }
+        case CkptAction::kFree:
+            if (a.arg < 0 || a.arg >= (int)snaps.size() || snaps[a.arg].t < 0)
+                return fail(AWE_EINVAL, "checkpoint schedule: free of empty snapshot %d", a.arg);
+            drop(snaps[a.arg].ua);
+            drop(snaps[a.arg].ub);
+            snaps[a.arg] = Snap{};
+            break;
+        case CkptAction::kYield: {
+            if (stop_at_visit) return AWE_OK;
+            if (a.arg != t || a.arg != nt - 1 - visited)
+                return fail(AWE_EINVAL, "checkpoint schedule: visit of %d at state %d", a.arg, t);
+            awe_status st = visit(t, ua);
+            if (st) return st;
+            ++visited;
+            break;
+        }
+        default:
+            return fail(AWE_EINVAL, "checkpoint schedule: bad action");
+        }
+    }
+    return AWE_OK;
+}
+
 }  // namespace awe
 
 struct awe_plan_s {
@@ -54,7 +168,7 @@ struct awe_plan_s {
     bool img_tuned = false;
 
     // device buffers owned by the plan
-    std::vector<void*> owned;
+    std::vector<std::pair<void*, size_t>> owned;   // allocation and its size
     size_t held = 0;
     float* coef = nullptr;
     float *d_ez = nullptr, *d_ey = nullptr, *d_ex = nullptr;
@@ -81,12 +195,17 @@ struct awe_plan_s {
     float *mu0 = nullptr, *mu1 = nullptr, *grad = nullptr;
     float* wavelet_copy = nullptr;
     float *b_t = nullptr, *b_du0 = nullptr, *b_du1 = nullptr, *b_dm = nullptr;   // linearised modelling
+    awe::Reversal rev;              // binomial checkpointing: schedule and executor state
+    std::vector<float*> rev_pool;   // its wavefield buffers
+    int rev_snaps = -1;             // snapshots of the schedule in rev (-1: none)
+    bool rev_mode = false;          // the stored states are binomial (else periodic)
     bool have_ckpt = false, have_grad = false;
 
     ~awe_plan_s();
     awe_status init(const awe_geometry* geo);
     awe_status set_model(const float* m, hipStream_t s);
     awe_status forward(const float* wavelet, float* traces, int K, hipStream_t s);
+    awe_status forward_binomial(const float* wavelet, float* traces, int snapshots, hipStream_t s);
     awe_status step(int n0, int nsteps, const float* wavelet, float* traces, hipStream_t s);
     awe_status adjoint(const float* resid, float* src_adj, float* grad_phys, hipStream_t s);
     awe_status born(const float* wavelet, const float* dm_phys, float* traces, hipStream_t s);
@@ -96,8 +215,15 @@ struct awe_plan_s {
     template <class T>
     awe_status upload(T** dst, const std::vector<T>& v);
     void release(void* p);
-    awe_status advance(const float* uc, const float* up, float* out, const float* q_row, hipStream_t s);
+    awe_status advance(const float* uc, const float* up, float* out, const float* q_row, float* rec_row,
+                       hipStream_t s);
+    awe::InjectOp src_op(float* field, const float* q_row, float* t_acc) const;
+    awe::SampleOp rec_op(float* row, const float* field) const;
     awe_status ensure_gradient_storage(int K);
+    awe_status ensure_binomial_storage(int snapshots);
+    awe_status ensure_adjoint_storage();
+    void release_periodic();
+    void release_binomial();
     awe_status tune(bool img, hipStream_t user_stream);
     float* pick_work_dst();
 };

@@ -13,35 +13,36 @@ inline unsigned blocks_for(int64_t n, int64_t cap = 65535 * 8) {
     return (unsigned)b;
 }
 
-// Source injection (Sec. IV sparse-point insertion; the transpose of the
-// multilinear interpolation).  One thread per touched grid node: the node's
-// CSR row lists (point, weight) pairs in ascending point order, so the sum is
-// deterministic and no atomics are needed.
-//   field[node] += C[node] * scale * sum_e w_e values[pt_e]
-//   imaging:  grad[node] += usnap[node] * (that same increment)
-//   save-t:   grad[node] += (that same increment)        (usnap == NULL)
+// Off-grid point operators (Sec. IV, sparse-point insertion and
+// interpolation), one launch for both.  Work items [0, nrows) inject, the
+// rest sample:
+//   injection (the transpose of the multilinear interpolation): one item per
+//     touched grid node; the node's CSR row lists (point, weight) pairs in
+//     ascending point order, so the sum is deterministic and needs no atomics.
+//       field[node] += C[node] * scale * sum_e w_e values[pt_e]
+//       imaging:  grad[node] += usnap[node] * (that same increment)
+//       save-t:   grad[node] += (that same increment)        (usnap == NULL)
+//   sampling: out[r] = scale * sum_k w[r][k] probe[node[r][k]].
+// The injected and the sampled arrays must not alias: the engine samples
+// u[n] (or mu[n+1]) while it injects into u[n+1] (or mu[n]).
 __global__ void __launch_bounds__(kBlock)
-inject_k(float* field, const float* coef, const int64_t* node, const int32_t* rowptr, const int32_t* pt,
-         const float* w, int32_t nrows, const float* values, float scale, const float* usnap, float* grad) {
-    const int j = blockIdx.x * kBlock + threadIdx.x;
-    if (j >= nrows) return;
-    float s = 0.f;
-    for (int e = rowptr[j]; e < rowptr[j + 1]; ++e) s += w[e] * values[pt[e]];
-    const int64_t i = node[j];
-    const float inc = coef[i] * (s * scale);
-    field[i] += inc;
-    if (grad) grad[i] += (usnap ? usnap[i] : 1.f) * inc;   // imaging (u * inc) or save-t (inc)
-}
-
-// Receiver interpolation: out[r] = scale * sum_k w[r][k] field[node[r][k]].
-__global__ void __launch_bounds__(kBlock)
-sample_k(float* out, const float* field, const int64_t* node, const float* w, int32_t npts, int32_t corners,
-         float scale) {
-    const int r = blockIdx.x * kBlock + threadIdx.x;
-    if (r >= npts) return;
-    float s = 0.f;
-    for (int k = 0; k < corners; ++k) s += w[(int64_t)r * corners + k] * field[node[(int64_t)r * corners + k]];
-    out[r] = s * scale;
+sparse_k(InjectOp a, SampleOp b) {
+    const int64_t total = (int64_t)a.nrows + b.npts;
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < total; j += (int64_t)gridDim.x * kBlock) {
+        if (j < a.nrows) {
+            float s = 0.f;
+            for (int e = a.rowptr[j]; e < a.rowptr[j + 1]; ++e) s += a.w[e] * a.values[a.pt[e]];
+            const int64_t i = a.node[j];
+            const float inc = a.coef[i] * (s * a.scale);
+            a.field[i] += inc;
+            if (a.grad) a.grad[i] += (a.usnap ? a.usnap[i] : 1.f) * inc;
+        } else {
+            const int64_t r = j - a.nrows;
+            float s = 0.f;
+            for (int k = 0; k < b.corners; ++k) s += b.w[r * b.corners + k] * b.field[b.node[r * b.corners + k]];
+            b.out[r] = s * b.scale;
+        }
+    }
 }
 
 struct PadGeo {
@@ -213,20 +214,10 @@ PadGeo pad_geo(const Layout& L, const int64_t phys[3], int nbl) {
 
 }  // namespace
 
-hipError_t launch_inject(float* field, const float* coef, const int64_t* node, const int32_t* rowptr,
-                         const int32_t* pt, const float* w, int32_t nrows, const float* values, float scale,
-                         const float* usnap, float* grad, hipStream_t s) {
-    if (nrows <= 0) return hipSuccess;
-    hipLaunchKernelGGL(inject_k, dim3(blocks_for(nrows)), dim3(kBlock), 0, s, field, coef, node, rowptr, pt, w,
-                       nrows, values, scale, usnap, grad);
-    return hipGetLastError();
-}
-
-hipError_t launch_sample(float* out, const float* field, const int64_t* node, const float* w, int32_t npts,
-                         int32_t corners, float scale, hipStream_t s) {
-    if (npts <= 0) return hipSuccess;
-    hipLaunchKernelGGL(sample_k, dim3(blocks_for(npts)), dim3(kBlock), 0, s, out, field, node, w, npts, corners,
-                       scale);
+hipError_t launch_sparse(const InjectOp& a, const SampleOp& b, hipStream_t s) {
+    const int64_t total = (int64_t)a.nrows + b.npts;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sparse_k, dim3(blocks_for(total)), dim3(kBlock), 0, s, a, b);
     return hipGetLastError();
 }
 
