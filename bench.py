@@ -77,11 +77,13 @@ def cpu_baseline(shot, dt, steps):
             "seconds": round(t, 3)}
 
 
-def bench_gradient(torch, awe, synth, n=400, nt=2000):
+def bench_gradient(torch, awe, synth, n=400, nt=2000, snapshots=20):
     """FWI gradient of the L2 trace misfit: 3-D, n^3 + 40-point layer, order 16,
     h = 12.5 m, nt samples, checkpoints every 50 steps, layered model with a
     +-10% Gaussian anomaly as the true model and its smoothed copy as the start.
-    Reports the gradient time against a plain forward of the same shot."""
+    Reports the gradient time against a plain forward of the same shot, and
+    the same gradient with binomial checkpointing over `snapshots` stored
+    states (fewer fields held, more forward steps recomputed)."""
     shot = synth.config_3d_gradient(n=n, nt=nt)
     K = shot.extra["checkpoint_every"]
     m_true = shot.extra["m_true"]
@@ -124,6 +126,32 @@ def bench_gradient(torch, awe, synth, n=400, nt=2000):
     t_fwd = f0.elapsed_time(f1) / 1e3
     info = plan.info()
     finite = bool(torch.isfinite(g).all().item())
+    binomial = None
+    if snapshots is not None and snapshots >= 0:
+        def gradient_binomial(ev):
+            ev[0].record()
+            tr = plan.forward(w, snapshots=snapshots)
+            ev[1].record()
+            _, resid = awe.misfit(tr, d_obs)
+            ev[2].record()
+            _, gb = plan.adjoint(resid, want_src_adj=False, want_grad=True)
+            ev[3].record()
+            torch.cuda.synchronize()
+            return gb
+
+        gradient_binomial(events())         # warm-up (allocates the buffer pool)
+        evb = events()
+        gb = gradient_binomial(evb)
+        steps, fields = awe.binomial_cost(shot.nt, snapshots)
+        t_b = evb[0].elapsed_time(evb[3]) / 1e3
+        binomial = {"snapshots": snapshots, "forward_steps": steps, "buffer_fields": fields,
+                    "gradient_s": t_b, "forward_s": evb[0].elapsed_time(evb[1]) / 1e3,
+                    "adjoint_with_recompute_s": evb[2].elapsed_time(evb[3]) / 1e3,
+                    "gradient_over_forward": t_b / t_fwd, "device_bytes": plan.info()["bytes"],
+                    "bitwise_equal_to_periodic": bool(torch.equal(gb, g))}
+        log(f"binomial checkpointing, {snapshots} snapshots: {t_b:.3f} s, {steps} forward steps, "
+            f"{binomial['device_bytes'] / 2**30:.1f} GiB held (periodic {info['bytes'] / 2**30:.1f} GiB), "
+            f"bitwise equal: {binomial['bitwise_equal_to_periodic']}")
     plan.close()
     upd = npad * (shot.nt - 1)
     log(f"gradient {shot.name}: {t_grad:.3f} s (forward+checkpoints {t_fwd_ckpt:.3f} s, adjoint+recompute "
@@ -139,7 +167,7 @@ def bench_gradient(torch, awe, synth, n=400, nt=2000):
         "gradient_algorithmic_GBps": 60.0 * upd / t_grad / 1e9,
         "device_bytes": info["bytes"], "launch_shapes": {"forward": info["forward_shape"],
                                                          "imaging": info["imaging_shape"]},
-        "finite": finite,
+        "finite": finite, "binomial": binomial,
     }
 
 
@@ -285,6 +313,8 @@ def main():
     ap.add_argument("--gradient-n", type=int, default=400,
                     help="physical points per axis of the gradient workload (0 = skip it)")
     ap.add_argument("--gradient-nt", type=int, default=2000, help="time samples of the gradient workload")
+    ap.add_argument("--binomial-snapshots", type=int, default=20,
+                    help="stored states of the binomial-checkpointing gradient (-1 = skip it)")
     ap.add_argument("--paper-example", type=int, default=1, help="run the paper's 3-D example workload (0 = skip)")
     ap.add_argument("--serve-requests", type=int, default=64, help="requests in the serving run (0 = skip)")
     ap.add_argument("--serve-scale", type=float, default=0.5, help="size/step scale of the serving mix")
@@ -369,7 +399,8 @@ def main():
     grad = None
     if args.gradient_n > 0:
         log("gradient workload ...")
-        grad = bench_gradient(torch, awe, synth, n=args.gradient_n, nt=args.gradient_nt)
+        grad = bench_gradient(torch, awe, synth, n=args.gradient_n, nt=args.gradient_nt,
+                              snapshots=args.binomial_snapshots)
 
     paper = None
     if args.paper_example:

@@ -392,7 +392,30 @@ struct TuneKey {
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, LaunchShape> g_tune_cache;
-constexpr int64_t kTuneMinPoints = 4 << 20;
+// Smallest grids worth timing: a 3-D tuning pass costs ~100 stencil launches
+// of the plan's own size, a 2-D pass a few milliseconds at most.
+constexpr int64_t kTuneMinPoints3 = 4 << 20;
+constexpr int64_t kTuneMinPoints2 = 1 << 16;
+
+// A shape tuned for a grid of the same dimensionality, order and mode with a
+// point count within a factor of two, if there is one: taken instead of
+// timing again (a server meets many nearby sizes).
+bool nearby_shape(const TuneKey& key, LaunchShape& out) {
+    const double pts = (double)key.n0 * key.n1 * key.n2;
+    double best = 2.0;
+    bool found = false;
+    for (const auto& kv : g_tune_cache) {
+        const TuneKey& o = kv.first;
+        if (o.dev != key.dev || o.ndim != key.ndim || o.half != key.half || o.img != key.img) continue;
+        const double r = std::max(pts, (double)o.n0 * o.n1 * o.n2) / std::min(pts, (double)o.n0 * o.n1 * o.n2);
+        if (r <= best) {
+            best = r;
+            out = kv.second;
+            found = true;
+        }
+    }
+    return found;
+}
 }  // namespace
 
 LaunchShape awe::default_shape(const Layout& L) {
@@ -409,7 +432,7 @@ awe_status Plan::tune(bool img, hipStream_t user_stream) {
         }
     }
     const char* off = std::getenv("AWE_AUTOTUNE");
-    if ((off && off[0] == '0') || L.points() < kTuneMinPoints) return AWE_OK;
+    if ((off && off[0] == '0') || L.points() < (g.ndim == 3 ? kTuneMinPoints3 : kTuneMinPoints2)) return AWE_OK;
     const TuneKey key{device, g.ndim, half, img ? 1 : 0, L.n[0], L.n[1], L.n[2]};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -418,14 +441,20 @@ awe_status Plan::tune(bool img, hipStream_t user_stream) {
             shape = it->second;
             return AWE_OK;
         }
+        LaunchShape near{};
+        if (g.ndim == 3 && nearby_shape(key, near)) {
+            shape = near;
+            g_tune_cache[key] = near;
+            return AWE_OK;
+        }
     }
     std::vector<LaunchShape> cand;
     if (g.ndim == 3) {
         for (int cfg : {0, 1, 3})
             for (int zc : {28, 42, 56, 70, 84}) cand.push_back({cfg, zc});
     } else {
-        for (int zc : {16, 32, 64, 128}) cand.push_back({0, zc});
-        for (int zc : {32, 64, 128}) cand.push_back({1, zc});
+        for (int zc : {4, 8, 16, 32, 64}) cand.push_back({0, zc});
+        for (int zc : {8, 16, 32, 64}) cand.push_back({1, zc});
     }
     hipStream_t s = user_stream;
     bool own = false;

@@ -30,7 +30,10 @@
 //   * the loads for plane z+1 are issued before the barrier of plane z so their
 //     latency hides behind the arithmetic of plane z;
 //   * each thread owns RY consecutive y rows, so y-neighbours inside its own
-//     rows come from registers.
+//     rows come from registers;
+//   * a thread row is one wavefront, so row indices and row offsets are
+//     wave-uniform (scalar registers): the vector registers hold the queue,
+//     the prefetched values and one column offset per lane.
 // 2-D uses the same scheme with a 64-point x row in LDS and no y axis.
 #pragma once
 
@@ -126,12 +129,15 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk) {
     constexpr int LH = TY + 2 * M;
     constexpr int NQ = 2 * M + 1;
     constexpr int NH = (2 * M + BY - 1) / BY;     // y-halo rows per thread row
+    constexpr bool kHyFull = (2 * M) % BY == 0;   // every thread row has NH halo rows
     __shared__ float lds[2][LH][LW];
 
     uint32_t bx, by, bz;
     if (!xcd_tile(g, bx, by, bz)) return;          // uniform over the workgroup
     const int tx = threadIdx.x;
-    const int ty = threadIdx.y;
+    // A thread row (64 lanes) is one wavefront, so everything indexed by ty
+    // is wave-uniform and lives in scalar registers.
+    const int ty = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
     const int x = bx * kTileX + tx;
     const int yb = by * TY;
     const int y0 = yb + ty * RY;
@@ -153,39 +159,42 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk) {
     const auto r_gr = slab_rsrc(MODE != kStepPlain ? a.grad + slab : a.out + slab, bytes);
     const uint32_t plane = (uint32_t)(sz * 4);     // bytes per z plane
     auto soff = [&](int z) { return (uint32_t)(z - z0 + M) * plane; };
-    auto voff = [&](int y, int xx) { return (uint32_t)(((int64_t)(y + M) * sy + xx + M) * 4); };
-
-    const bool xin = x < g.nx;                     // this lane owns a grid point
-    const bool xld = x < g.nx + M;                 // this lane's column is in the allocation
-    uint32_t o_in[RY], o_ld[RY];                   // per-row offsets for owned / loadable points
+    // Byte offsets from the slab base: the column goes in the per-lane vector
+    // offset, the row (wave-uniform) joins the plane in the scalar offset.
+    // Loads stay inside the allocation by construction: columns and rows are
+    // clamped to the last ghost column / row, and no owned point uses a value
+    // loaded from beyond them.  Lanes that own no point get kOob for the
+    // arrays read only at owned points (reads 0) and for stores (dropped).
+    auto colb = [&](int xx) { return (uint32_t)((min(xx, g.nx + M - 1) + M) * 4); };
+    auto rowb = [&](int y) { return (uint32_t)((int64_t)(min(y, g.ny + M - 1) + M) * sy * 4); };
+    const uint32_t v_ld = colb(x);
+    const uint32_t v_st = x < g.nx ? (uint32_t)((x + M) * 4) : kOob;
+    uint32_t s_row[RY];
 #pragma unroll
-    for (int r = 0; r < RY; ++r) {
-        const uint32_t o = voff(y0 + r, x);
-        o_in[r] = (xin && y0 + r < g.ny) ? o : kOob;
-        o_ld[r] = (xld && y0 + r < g.ny + M) ? o : kOob;
-    }
+    for (int r = 0; r < RY; ++r) s_row[r] = rowb(y0 + r);
+    // per-row store offsets (kOob where the row owns no point): a branch per
+    // row would split the unrolled plane into blocks the scheduler cannot mix
+    uint32_t v_str[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) v_str[r] = (y0 + r < g.ny) ? v_st : kOob;
     // x halo: lanes tx < M load the left columns, lanes tx >= 64-M the right ones.
     const bool hl = tx < M;
     const bool hr = tx >= kTileX - M;
-    const int hx = hl ? ((int)bx * kTileX - M + tx) : ((int)bx * kTileX + M + tx);
     const int hlx = hl ? tx : (tx + 2 * M);        // LDS column of the halo value
-    uint32_t o_hx[RY];
-#pragma unroll
-    for (int r = 0; r < RY; ++r)
-        o_hx[r] = ((hl || hr) && hx < g.nx + M && y0 + r < g.ny + M) ? voff(y0 + r, hx) : kOob;
+    const uint32_t v_hx = (hl || hr) ? colb(hl ? x - M : x + M) : kOob;
     // y halo: 2M rows (M above, M below the tile), 64 columns; thread row ty
     // loads halo rows h = ty, ty + BY, ... < 2M.
     int hyrow[NH];
-    uint32_t o_hy[NH];
+    uint32_t s_hy[NH];
 #pragma unroll
     for (int i = 0; i < NH; ++i) {
         const int h = ty + i * BY;
         const int y = (h < M) ? (yb - M + h) : (yb + TY + (h - M));
         hyrow[i] = (h < M) ? h : (TY + h);
-        o_hy[i] = ((h < 2 * M) && xld && (y < g.ny + M)) ? voff(y, x) : kOob;
+        s_hy[i] = rowb(y);
     }
 
-    const float exv = xin ? a.eta_x[x] : 0.f;
+    const float exv = x < g.nx ? a.eta_x[x] : 0.f;
     float eyv[RY];
 #pragma unroll
     for (int r = 0; r < RY; ++r) eyv[r] = (y0 + r < g.ny) ? a.eta_y[y0 + r] : 0.f;
@@ -195,7 +204,7 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk) {
 #pragma unroll
     for (int j = 1; j < NQ; ++j)
 #pragma unroll
-        for (int r = 0; r < RY; ++r) q[r][j] = bload(r_uc, o_ld[r], soff(z0 - M + j - 1));
+        for (int r = 0; r < RY; ++r) q[r][j] = bload(r_uc, v_ld, soff(z0 - M + j - 1) + s_row[r]);
     drain_vmem();
 
     float fr[RY], pv[RY], cv[RY], sv[RY], gv[RY], hxv[RY], hyv[NH], ezn;
@@ -206,17 +215,20 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk) {
         const uint32_t so = soff(z), sf = soff(z + M);
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-            fr[r] = bload(r_uc, o_ld[r], sf);
-            pv[r] = bload<AWE_CPOL_STREAM>(r_up, o_in[r], so);
-            cv[r] = bload<AWE_CPOL_STREAM>(r_cf, o_in[r], so);
+            fr[r] = bload(r_uc, v_ld, sf + s_row[r]);
+            // arrays read only at owned points: lanes past the grid read
+            // nothing (a clamped column can sit in a line of its own)
+            pv[r] = bload<AWE_CPOL_STREAM>(r_up, v_st, so + s_row[r]);
+            cv[r] = bload<AWE_CPOL_STREAM>(r_cf, v_st, so + s_row[r]);
             if (MODE == kStepImaging || MODE == kStepBorn) {
-                sv[r] = bload<AWE_CPOL_STREAM>(r_us, o_in[r], so);
-                gv[r] = bload<AWE_CPOL_STREAM>(r_gr, o_in[r], so);
+                sv[r] = bload<AWE_CPOL_STREAM>(r_us, v_st, so + s_row[r]);
+                gv[r] = bload<AWE_CPOL_STREAM>(r_gr, v_st, so + s_row[r]);
             }
-            hxv[r] = bload(r_uc, o_hx[r], so);
+            hxv[r] = bload(r_uc, v_hx, so + s_row[r]);
         }
 #pragma unroll
-        for (int i = 0; i < NH; ++i) hyv[i] = bload(r_uc, o_hy[i], so);
+        for (int i = 0; i < NH; ++i)
+            if (kHyFull || ty + i * BY < 2 * M) hyv[i] = bload(r_uc, v_ld, so + s_hy[i]);
     };
     fetch(z0);
 
@@ -238,7 +250,7 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk) {
         }
 #pragma unroll
         for (int i = 0; i < NH; ++i)
-            if (ty + i * BY < 2 * M) lds[b][hyrow[i]][M + tx] = hyv[i];
+            if (kHyFull || ty + i * BY < 2 * M) lds[b][hyrow[i]][M + tx] = hyv[i];
 
         float p[RY], c[RY], s[RY], gg[RY];
 #pragma unroll
@@ -282,9 +294,9 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk) {
             const float av = (ezv + eyv[r] + exv) * c[r] * k.inv_dt;
             float t = c[r] * lap + av * (p[r] - u0);
             if (MODE == kStepBorn) t -= (c[r] * k.inv_dt2) * (s[r] * gg[r]);
-            bstore<AWE_CPOL_STREAM>(r_out, (u0 - p[r]) + u0 + t, o_in[r], so);
-            if (MODE == kStepImaging) bstore<AWE_CPOL_STREAM>(r_gr, gg[r] + s[r] * t, o_in[r], so);
-            if (MODE == kStepSaveT) bstore<AWE_CPOL_STREAM>(r_gr, t, o_in[r], so);
+            bstore<AWE_CPOL_STREAM>(r_out, (u0 - p[r]) + u0 + t, v_str[r], so + s_row[r]);
+            if (MODE == kStepImaging) bstore<AWE_CPOL_STREAM>(r_gr, gg[r] + s[r] * t, v_str[r], so + s_row[r]);
+            if (MODE == kStepSaveT) bstore<AWE_CPOL_STREAM>(r_gr, t, v_str[r], so + s_row[r]);
         }
     };
     // before plane z0 the queue holds planes z0-M .. z0+M-1 in physical slots

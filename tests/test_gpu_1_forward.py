@@ -192,3 +192,36 @@ def test_autotuned_plan_matches_forced_shape(monkeypatch):
     tuned = _forward_with_env(monkeypatch, shot, dt, {"AWE_TILE": None, "AWE_AUTOTUNE": None})
     forced = _forward_with_env(monkeypatch, shot, dt, {"AWE_TILE": "1,28"})
     assert np.array_equal(tuned[0], forced[0]) and np.array_equal(tuned[1], forced[1])
+
+
+@pytest.mark.parametrize("order", [4, 16])
+def test_autotuned_2d_plan_matches_forced_shape(monkeypatch, order):
+    # 2-D grids from 64K points are tuned (zchunks down to 4 planes per wave)
+    shot = small_2d_shot(320 + order, order, shape=(330, 290), nbl=12, nt=60)
+    dt = shot_dt(shot)
+    tuned = _forward_with_env(monkeypatch, shot, dt, {"AWE_TILE": None, "AWE_AUTOTUNE": None})
+    for cfg in ("0,4", "1,8", "0,64"):
+        forced = _forward_with_env(monkeypatch, shot, dt, {"AWE_TILE": cfg})
+        assert np.array_equal(tuned[0], forced[0]) and np.array_equal(tuned[1], forced[1]), cfg
+
+
+def test_nearby_3d_sizes_reuse_a_tuned_shape(monkeypatch):
+    # a second plan within a factor two of a tuned size takes its shape
+    # without timing; its results equal a forced run of that shape
+    import paper_1608_08658_amd as awe
+    rng = np.random.default_rng(6)
+    outs = []
+    for n in (150, 156):
+        shape = (n, n, n)
+        v = synth.layered_velocity(shape, rng, nlayers=(3, 5))
+        shot = synth.Shot(f"near-{n}", shape, (10.0,) * 3, 16, 12, 12, 1.0 / v ** 2,
+                          np.array([[300.0, 700.0, 700.0]]), np.array([[25.0, 100.0, 900.0]]), 20.0,
+                          damp_vref=float(v.min()))
+        dt = shot_dt(shot)
+        for k in ("AWE_TILE", "AWE_AUTOTUNE"):
+            monkeypatch.delenv(k, raising=False)
+        plan = gpu_plan(shot, dt)
+        outs.append(plan.info()["forward_shape"])
+        plan.close()
+    log(f"tuned {outs[0]}, reused {outs[1]}")
+    assert outs[0] == outs[1]
