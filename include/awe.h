@@ -246,12 +246,14 @@ awe_status awe_misfit(const float* traces_dev, const float* d_obs_dev, int64_t n
 /* ---------------------------------------------------------------------------
  * Serving: a shot server with continuous batching on the current device.
  * Requests carry their own geometry, model and wavelet (host memory, copied
- * at submit).  An engine thread admits queued requests while the sum of
- * their awe_footprint stays within hbm_fraction of the device memory that
- * was free at creation and at most max_active run at once; every iteration
- * advances every running request by up to chunk_steps time steps, and a
- * request that finishes is retired and its traces copied to traces_host
- * (host [nt][nrec], kept by the server until the request is done).
+ * at submit).  An engine thread admits queued requests in arrival order
+ * while the sum of their awe_footprint stays within hbm_fraction of the
+ * device memory that was free at creation and at most max_active run at
+ * once.  Each running request advances on its own stream in chunks of
+ * chunk_steps time steps, two chunks in flight, independently of the others
+ * (no batch-wide barrier); a request that finishes is retired and its traces
+ * copied to traces_host (host [nt][nrec], kept by the server until the
+ * request is done).  Stats' "iterations" counts passes of the engine loop.
  * ------------------------------------------------------------------------- */
 enum { AWE_REQ_QUEUED = 0, AWE_REQ_RUNNING = 1, AWE_REQ_DONE = 2, AWE_REQ_FAILED = 3 };
 

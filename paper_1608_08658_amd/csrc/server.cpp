@@ -1,14 +1,16 @@
 // Shot server with continuous batching (extern "C" awe_server_* of awe.h).
 //
 // Requests are admitted against a device-memory budget and a cap on running
-// requests.  The engine thread runs iterations: each iteration enqueues up to
-// `chunk` time steps of every running request on that request's own stream,
-// so the kernels of different shots overlap on the device, and a request
-// that arrives while others run joins at the next iteration boundary instead
-// of waiting for the batch to drain.  Finished requests are retired (traces
-// copied out, memory released) as soon as their stream reaches the end, which
-// frees budget for the queue.  Each request's arithmetic is exactly that of a
-// plan run alone: the steps are the same kernels on the same data, only
+// requests.  Every running request advances on its own stream in chunks of
+// `chunk` time steps, with two chunks in flight: the engine thread polls each
+// request's chunk events and enqueues its next chunk as soon as one
+// completes, so the kernels of different shots overlap on the device, a
+// short request is never held back by a long one (there is no batch-wide
+// barrier), and a request that arrives while others run is admitted as soon
+// as a slot and memory are free.  Finished requests are retired (traces
+// copied out, memory released) when their last chunk completes, which frees
+// budget for the queue.  Each request's arithmetic is exactly that of a plan
+// run alone: the steps are the same kernels on the same data, only
 // interleaved in time with other requests.
 #include <hip/hip_runtime.h>
 
@@ -47,7 +49,8 @@ struct Request {
     // device side while running
     awe_plan plan = nullptr;
     hipStream_t stream = nullptr;
-    hipEvent_t chunk_done = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};   // completion of the chunks in flight (ring)
+    int ev_head = 0, inflight = 0;
     float* d_m = nullptr;
     float* d_wav = nullptr;
     float* d_tr = nullptr;
@@ -84,12 +87,15 @@ void awe_server_s::finish(Request* r, int state, const std::string& err) {
     // caller does not hold mu
     if (r->plan) awe_plan_destroy(r->plan);
     r->plan = nullptr;
-    if (r->chunk_done) (void)hipEventDestroy(r->chunk_done);
+    if (r->stream) (void)hipStreamSynchronize(r->stream);
+    for (hipEvent_t& e : r->ev) {
+        if (e) (void)hipEventDestroy(e);
+        e = nullptr;
+    }
     if (r->stream) (void)hipStreamDestroy(r->stream);
     for (float* p : {r->d_m, r->d_wav, r->d_tr})
         if (p) (void)hipFree(p);
     r->d_m = r->d_wav = r->d_tr = nullptr;
-    r->chunk_done = nullptr;
     r->stream = nullptr;
     std::vector<float>().swap(r->m);
     std::vector<float>().swap(r->wavelet);
@@ -112,7 +118,8 @@ bool awe_server_s::start(Request* r, std::string& err) {
     awe_status st = awe_plan_create(&r->g, &r->plan);
     if (st) { err = awe_last_error(); return false; }
     if (!hip_ok(hipStreamCreateWithFlags(&r->stream, hipStreamNonBlocking), "hipStreamCreate")) return false;
-    if (!hip_ok(hipEventCreateWithFlags(&r->chunk_done, hipEventDisableTiming), "hipEventCreate")) return false;
+    for (hipEvent_t& e : r->ev)
+        if (!hip_ok(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate")) return false;
     const size_t nm = r->m.size(), nw = r->wavelet.size(), ntr = (size_t)r->g.nt * r->g.nrec;
     if (!hip_ok(hipMalloc(&r->d_m, nm * sizeof(float)), "hipMalloc")) return false;
     if (nw && !hip_ok(hipMalloc(&r->d_wav, nw * sizeof(float)), "hipMalloc")) return false;
@@ -164,44 +171,63 @@ void awe_server_s::run() {
                 finish(r, AWE_REQ_FAILED, err);
             }
         }
-        // one iteration: enqueue a chunk of every running request
+        // keep two chunks in flight per running request; retire on completion
         std::vector<Request*> running;
         {
             std::lock_guard<std::mutex> lk(mu);
             running = active;
         }
+        bool progressed = !admitted.empty();
         for (Request* r : running) {
-            if (r->copying) continue;
-            const int last = r->g.nt - 1;
-            const int n = std::min(chunk, last - r->next);
-            if (n > 0) {
-                awe_status st = r->plan->step(r->next, n, r->d_wav, r->d_tr, r->stream);
-                if (st) {
-                    std::string err = awe_last_error();
-                    { std::lock_guard<std::mutex> lk(mu); active.erase(std::find(active.begin(), active.end(), r)); }
-                    finish(r, AWE_REQ_FAILED, err);
-                    continue;
+            std::string err;
+            bool failed = false;
+            // completed chunks, oldest first (a stream's events complete in order)
+            while (r->inflight > 0) {
+                const int tail = (r->ev_head - r->inflight + 2) % 2;
+                const hipError_t e = hipEventQuery(r->ev[tail]);
+                if (e == hipErrorNotReady) break;
+                if (e != hipSuccess) {
+                    err = hipGetErrorString(e);
+                    failed = true;
+                    break;
                 }
-                r->next += n;
+                --r->inflight;
+                progressed = true;
             }
-            if (r->next >= last) {
-                const size_t ntr = (size_t)r->g.nt * r->g.nrec;
-                if (ntr) (void)hipMemcpyAsync(r->traces_host, r->d_tr, ntr * sizeof(float), hipMemcpyDeviceToHost,
-                                              r->stream);
-                r->copying = true;
+            while (!failed && !r->copying && r->inflight < 2) {
+                const int last = r->g.nt - 1;
+                const int n = std::min(chunk, last - r->next);
+                if (n > 0) {
+                    if (r->plan->step(r->next, n, r->d_wav, r->d_tr, r->stream)) {
+                        err = awe_last_error();
+                        failed = true;
+                        break;
+                    }
+                    r->next += n;
+                }
+                if (r->next >= last) {
+                    const size_t ntr = (size_t)r->g.nt * r->g.nrec;
+                    if (ntr) (void)hipMemcpyAsync(r->traces_host, r->d_tr, ntr * sizeof(float), hipMemcpyDeviceToHost,
+                                                  r->stream);
+                    r->copying = true;
+                }
+                const hipError_t e = hipEventRecord(r->ev[r->ev_head], r->stream);
+                if (e != hipSuccess) {
+                    err = hipGetErrorString(e);
+                    failed = true;
+                    break;
+                }
+                r->ev_head = (r->ev_head + 1) % 2;
+                ++r->inflight;
+                progressed = true;
             }
-            (void)hipEventRecord(r->chunk_done, r->stream);
-        }
-        // wait for this iteration's chunks; retire finished requests
-        for (Request* r : running) {
-            if (!r->chunk_done) continue;
-            hipError_t e = hipEventSynchronize(r->chunk_done);
-            if (e != hipSuccess || r->copying) {
+            if (failed || (r->copying && r->inflight == 0)) {
                 { std::lock_guard<std::mutex> lk(mu); active.erase(std::find(active.begin(), active.end(), r)); }
-                finish(r, e == hipSuccess ? AWE_REQ_DONE : AWE_REQ_FAILED,
-                       e == hipSuccess ? "" : hipGetErrorString(e));
+                finish(r, failed ? AWE_REQ_FAILED : AWE_REQ_DONE, err);
+                progressed = true;
             }
         }
+        if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(20));
         std::lock_guard<std::mutex> lk(mu);
         ++iterations;
     }
