@@ -72,6 +72,7 @@ def cpu_baseline(shot, dt, steps):
     t = time.perf_counter() - t0
     npad = int(np.prod(prob.padded_shape))
     return {"value": npad * steps / t, "unit": "grid-pt updates/s", "cores": 1, "kind": "oracle",
+            "host_cpus": os.cpu_count(), "host_cpus_allowed": len(os.sched_getaffinity(0)),
             "sample": f"{steps} steps (with injection and receiver sampling) of the same "
                       f"{'x'.join(map(str, prob.padded_shape))} grid, NumPy FP64, single-threaded",
             "seconds": round(t, 3)}
