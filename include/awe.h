@@ -11,8 +11,9 @@
  * absorbing layer of nbl points on every side of the physical model, source
  * injection and receiver interpolation at off-grid points (Sec. IV).  The
  * adjoint run backwards in time (Eq. 4, Listing 2) and the adjoint-state
- * gradient of the L2 trace misfit (Eqs. 2-3) are provided with periodic
- * wavefield checkpointing and recomputation.
+ * gradient of the L2 trace misfit (Eqs. 2-3) are provided with periodic or
+ * binomial wavefield checkpointing and recomputation, and the linearised
+ * (Born) operator whose adjoint that gradient is.
  *
  * Conventions for every call
  *   - Layout: arrays are FP32, C order, axis 0 = depth (slowest), the last
