@@ -58,10 +58,13 @@ struct StepArgs {
                                  // save-t: receives t; born: the background's t (read)
 };
 
+struct FusedSparse;
+
 // Kernel launchers (kernels_stencil.hip, kernels_aux.hip).  All return the
-// launch status; none synchronise.
+// launch status; none synchronise.  A plain step may take over the point
+// operators of its time step (fs, see FusedSparse).
 hipError_t launch_step(const Layout& L, const StencilCoef& k, const StepArgs& a, int mode,
-                       int tile_cfg, int zchunk, hipStream_t s);
+                       int tile_cfg, int zchunk, hipStream_t s, const FusedSparse* fs = nullptr);
 int num_tile_cfgs(int ndim);
 int tile_rows(int ndim, int tile_cfg);   // y rows (3-D) or z chunks per block (2-D)
 
@@ -90,6 +93,19 @@ struct SampleOp {
     int32_t corners = 0;
 };
 hipError_t launch_sparse(const InjectOp& a, const SampleOp& b, hipStream_t s);
+
+// The point operators of one plain time step carried out by the stencil
+// launch itself: extra workgroups past the tile grid sample the step's input
+// u[n] (which the launch only reads), and the few workgroups whose tile holds
+// an injection node add its increment to u[n+1] before storing it, with the
+// same arithmetic as launch_sparse (u[n+1] is rounded first, then the
+// increment added).  Injection is fused only for at most kFuseMaxNodes nodes.
+constexpr int kFuseMaxNodes = 8;
+struct FusedSparse {
+    InjectOp inj;                      // inj.field is the step's output; nrows <= kFuseMaxNodes
+    const int32_t* inj_zyx = nullptr;  // [nrows][3]: (z, y, x) grid indices of the nodes (y = 0 in 2-D)
+    SampleOp smp;                      // smp.field is the step's input
+};
 hipError_t launch_coef(float* coef, const float* m_phys, const Layout& L, const int64_t phys[3], int nbl,
                        const double* eta_z, const double* eta_y, const double* eta_x, double dt, hipStream_t s);
 hipError_t launch_minmax(const float* m, int64_t n, float* partial /* [3 * blocks] */, int blocks, hipStream_t s);

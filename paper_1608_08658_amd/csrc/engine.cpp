@@ -361,6 +361,18 @@ awe_status Plan::init(const awe_geometry* geo) {
         (st = upload(&src_csr.pt, cs.pt)) || (st = upload(&src_csr.w, cs.w)))
         return st;
     src_csr.nrows = (int32_t)cs.node.size();
+    // grid indices (z, y, x) of the source nodes, for injection fused into the stencil
+    if (src_csr.nrows > 0 && src_csr.nrows <= kFuseMaxNodes) {
+        std::vector<int32_t> zyx;
+        for (int64_t node : cs.node) {
+            const int64_t rel = node - L.origin;
+            const int64_t z = rel / L.sz, y = (rel % L.sz) / L.sy, x = (rel % L.sz) % L.sy;
+            zyx.insert(zyx.end(), {(int32_t)z, (int32_t)y, (int32_t)x});
+        }
+        if ((st = upload(&src_zyx, zyx))) return st;
+    }
+    const char* fuse_env = std::getenv("AWE_FUSE");
+    fuse_sparse = !(fuse_env && fuse_env[0] == '0');
     if ((st = upload(&rec_csr.node, cr.node)) || (st = upload(&rec_csr.rowptr, cr.rowptr)) ||
         (st = upload(&rec_csr.pt, cr.pt)) || (st = upload(&rec_csr.w, cr.w)))
         return st;
@@ -556,15 +568,26 @@ SampleOp Plan::rec_op(float* row, const float* field) const {
     return b;
 }
 
-// One step of the recurrence from (uc, up) into out, then one launch that
-// injects the point source into out and, if rec_row is given, records the
-// receivers' samples of uc (the previous step's result, left untouched by
-// this step) into rec_row.
+// One step of the recurrence from (uc, up) into out with the point source
+// injected into out and, if rec_row is given, the receivers' samples of uc
+// (the previous step's result, left untouched by this step) recorded into
+// rec_row.  With few source nodes the stencil launch does both itself (one
+// launch per step); otherwise a second launch follows it.
 awe_status Plan::advance(const float* uc, const float* up, float* out, const float* q_row, float* rec_row,
                          hipStream_t s) {
     StepArgs a{uc, up, out, coef, d_ez, d_ey, d_ex, nullptr, nullptr};
+    const InjectOp inj = src_op(out, q_row, nullptr);
+    const SampleOp smp = rec_op(rec_row, uc);
+    if (fuse_sparse && inj.nrows <= kFuseMaxNodes && (inj.nrows == 0 || src_zyx)) {
+        FusedSparse fs;
+        fs.inj = inj;
+        fs.inj_zyx = src_zyx;
+        fs.smp = smp;
+        AWE_HIP(launch_step(L, k, a, kStepPlain, fwd_shape.cfg, fwd_shape.zchunk, s, &fs));
+        return AWE_OK;
+    }
     AWE_HIP(launch_step(L, k, a, kStepPlain, fwd_shape.cfg, fwd_shape.zchunk, s));
-    AWE_HIP(launch_sparse(src_op(out, q_row, nullptr), rec_op(rec_row, uc), s));
+    AWE_HIP(launch_sparse(inj, smp, s));
     return AWE_OK;
 }
 

@@ -179,6 +179,8 @@ struct awe_plan_s {
     int64_t* rec_node = nullptr;
     float* rec_w = nullptr;
     awe::DeviceCsr src_csr, rec_csr;
+    int32_t* src_zyx = nullptr;     // (z, y, x) of the source nodes when few enough to fuse
+    bool fuse_sparse = true;        // point operators inside the stencil launch (AWE_FUSE=0: off)
     float* d_partial = nullptr;
     double* d_mpart = nullptr;
 

@@ -29,17 +29,21 @@ __global__ void __launch_bounds__(kBlock)
 sparse_k(InjectOp a, SampleOp b) {
     const int64_t total = (int64_t)a.nrows + b.npts;
     for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < total; j += (int64_t)gridDim.x * kBlock) {
+        // explicit fused multiply-adds: the stencil launch's fused form of
+        // these operators (stencil_impl.hpp) computes the same expressions
         if (j < a.nrows) {
             float s = 0.f;
-            for (int e = a.rowptr[j]; e < a.rowptr[j + 1]; ++e) s += a.w[e] * a.values[a.pt[e]];
+            for (int e = a.rowptr[j]; e < a.rowptr[j + 1]; ++e) s = __builtin_fmaf(a.w[e], a.values[a.pt[e]], s);
             const int64_t i = a.node[j];
-            const float inc = a.coef[i] * (s * a.scale);
-            a.field[i] += inc;
+            const float cs = s * a.scale;
+            const float inc = a.coef[i] * cs;
+            a.field[i] = __builtin_fmaf(a.coef[i], cs, a.field[i]);
             if (a.grad) a.grad[i] += (a.usnap ? a.usnap[i] : 1.f) * inc;
         } else {
             const int64_t r = j - a.nrows;
             float s = 0.f;
-            for (int k = 0; k < b.corners; ++k) s += b.w[r * b.corners + k] * b.field[b.node[r * b.corners + k]];
+            for (int k = 0; k < b.corners; ++k)
+                s = __builtin_fmaf(b.w[r * b.corners + k], b.field[b.node[r * b.corners + k]], s);
             b.out[r] = s * b.scale;
         }
     }

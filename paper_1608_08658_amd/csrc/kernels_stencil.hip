@@ -6,9 +6,9 @@
 namespace awe {
 
 hipError_t launch_step_lo(const Layout& L, const StencilCoef& k, const StepArgs& a, int mode, int cfg, int zchunk,
-                          hipStream_t s);
+                          hipStream_t s, const FusedSparse& fs);
 hipError_t launch_step_hi(const Layout& L, const StencilCoef& k, const StepArgs& a, int mode, int cfg, int zchunk,
-                          hipStream_t s);
+                          hipStream_t s, const FusedSparse& fs);
 
 int num_tile_cfgs(int ndim) { return ndim == 3 ? 4 : 2; }
 
@@ -21,16 +21,24 @@ int tile_rows(int ndim, int cfg) {
 }
 
 hipError_t launch_step(const Layout& L, const StencilCoef& k, const StepArgs& a, int mode, int cfg, int zchunk,
-                       hipStream_t s) {
+                       hipStream_t s, const FusedSparse* fused) {
     if (zchunk < 1 || cfg < 0 || cfg >= num_tile_cfgs(L.ndim) || mode < 0 || mode > kStepSaveT)
+        return hipErrorInvalidValue;
+    const FusedSparse none{};
+    const FusedSparse& fs = fused ? *fused : none;
+    // fused point operators: plain steps only, injection into the output,
+    // sampling of the input, at most kFuseMaxNodes injection nodes
+    if (fused && (mode != kStepPlain || fs.inj.nrows > kFuseMaxNodes || fs.inj.nrows < 0 || fs.smp.npts < 0 ||
+                  (fs.inj.nrows > 0 && (fs.inj.field != a.out || !fs.inj_zyx)) ||
+                  (fs.smp.npts > 0 && fs.smp.field != a.uc)))
         return hipErrorInvalidValue;
     // a workgroup's slab (zchunk + 2M planes) must be addressable with 31-bit
     // byte offsets; tiling never changes results, so shorten the chunk if not
     const int64_t max_planes = 0x7FFFFFF0ll / (4 * L.sz);
     if (max_planes < 2 * L.half + 2) return hipErrorInvalidValue;
     if (zchunk > max_planes - 2 * L.half - 1) zchunk = (int)(max_planes - 2 * L.half - 1);
-    if (L.half >= 1 && L.half <= 4) return launch_step_lo(L, k, a, mode, cfg, zchunk, s);
-    if (L.half >= 5 && L.half <= 8) return launch_step_hi(L, k, a, mode, cfg, zchunk, s);
+    if (L.half >= 1 && L.half <= 4) return launch_step_lo(L, k, a, mode, cfg, zchunk, s, fs);
+    if (L.half >= 5 && L.half <= 8) return launch_step_hi(L, k, a, mode, cfg, zchunk, s, fs);
     return hipErrorInvalidValue;
 }
 

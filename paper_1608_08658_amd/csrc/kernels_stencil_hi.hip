@@ -4,12 +4,12 @@
 namespace awe {
 
 hipError_t launch_step_hi(const Layout& L, const StencilCoef& k, const StepArgs& a, int mode, int cfg, int zchunk,
-                          hipStream_t s) {
+                          hipStream_t s, const FusedSparse& fs) {
     switch (L.half) {
-        case 5: return launch_m<5>(L, k, a, mode, cfg, zchunk, s);
-        case 6: return launch_m<6>(L, k, a, mode, cfg, zchunk, s);
-        case 7: return launch_m<7>(L, k, a, mode, cfg, zchunk, s);
-        case 8: return launch_m<8>(L, k, a, mode, cfg, zchunk, s);
+        case 5: return launch_m<5>(L, k, a, mode, cfg, zchunk, s, fs);
+        case 6: return launch_m<6>(L, k, a, mode, cfg, zchunk, s, fs);
+        case 7: return launch_m<7>(L, k, a, mode, cfg, zchunk, s, fs);
+        case 8: return launch_m<8>(L, k, a, mode, cfg, zchunk, s, fs);
         default: return hipErrorInvalidValue;
     }
 }

@@ -74,8 +74,41 @@ struct Geo3 {
     int32_t nz, ny, nx;
     int64_t sy, sz, origin;
     uint32_t gx, gy, ntiles;     // tile grid (x tiles, y tiles) and total tiles incl. z chunks
+    uint32_t ngrid;              // workgroups of the tile grid (ntiles rounded up to the XCD count);
+                                 // workgroups past it sample (fused point operators)
     int64_t total;               // elements in each field's allocation
 };
+
+// Fused point operators of a plain step (FusedSparse): one receiver sample
+// per thread of a sampling workgroup, and one injection row, each with the
+// arithmetic of sparse_k (the same explicit fused multiply-adds).
+__device__ __forceinline__ void fused_sample(const SampleOp& b, int64_t r) {
+    if (r >= b.npts) return;
+    float s = 0.f;
+    for (int k = 0; k < b.corners; ++k) s = __builtin_fmaf(b.w[r * b.corners + k], b.field[b.node[r * b.corners + k]], s);
+    b.out[r] = s * b.scale;
+}
+// Orders the workgroup's stores of its tile before any of its threads reads
+// them back: every wave waits for its stores to complete (vector-memory
+// counter at zero; gfx9 counts stores there) before the barrier, and the
+// reader then reads through to L2.  The fences keep the compiler from moving
+// memory operations across.
+__device__ __forceinline__ void tile_stores_visible() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    drain_vmem();
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+// Injection row j added to the output after the workgroup's sweep: the
+// value the sweep stored (read from L2, past this CU's L1) plus the increment.
+// Only the workgroup whose tile holds the node touches it.
+__device__ __forceinline__ void inj_apply(const InjectOp& a, int j) {
+    float s = 0.f;
+    for (int e = a.rowptr[j]; e < a.rowptr[j + 1]; ++e) s = __builtin_fmaf(a.w[e], a.values[a.pt[e]], s);
+    const int64_t i = a.node[j];
+    const float v = __hip_atomic_load(a.field + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    a.field[i] = __builtin_fmaf(a.coef[i], s * a.scale, v);
+}
 
 // Workgroups are dealt to the 8 XCDs round-robin by linear id, and each XCD
 // has its own L2.  Remap so that XCD k runs the contiguous logical range
@@ -83,7 +116,7 @@ struct Geo3 {
 // share halo rows and columns then run at the same time on the same L2.
 constexpr uint32_t kXcds = 8;
 __device__ __forceinline__ bool xcd_tile(const Geo3& g, uint32_t& bx, uint32_t& by, uint32_t& bz) {
-    const uint32_t per = gridDim.x / kXcds;
+    const uint32_t per = g.ngrid / kXcds;
     const uint32_t lin = (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
     if (lin >= g.ntiles) return false;
     bx = lin % g.gx;
@@ -119,7 +152,7 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, float v, uint32
 
 template <int M, int BY, int RY, int MODE>
 __global__ void __launch_bounds__(kTileX * BY)
-step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk) {
+step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk, FusedSparse fs) {
     constexpr int TY = BY * RY;
     // LDS row pitch of 128 dwords (two 64-dword units): every y-neighbour pair
     // (y-k, y+k) is then one ds_read2st64 with immediate offsets, instead of
@@ -132,6 +165,10 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk) {
     constexpr bool kHyFull = (2 * M) % BY == 0;   // every thread row has NH halo rows
     __shared__ float lds[2][LH][LW];
 
+    if (blockIdx.x >= g.ngrid) {                   // a sampling workgroup
+        fused_sample(fs.smp, (int64_t)(blockIdx.x - g.ngrid) * (kTileX * BY) + threadIdx.y * kTileX + threadIdx.x);
+        return;
+    }
     uint32_t bx, by, bz;
     if (!xcd_tile(g, bx, by, bz)) return;          // uniform over the workgroup
     const int tx = threadIdx.x;
@@ -198,6 +235,7 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk) {
     float eyv[RY];
 #pragma unroll
     for (int r = 0; r < RY; ++r) eyv[r] = (y0 + r < g.ny) ? a.eta_y[y0 + r] : 0.f;
+
 
     // register queue of the z-neighbourhood: q[r][j] = uc(z - M + j)
     float q[RY][NQ];
@@ -310,20 +348,44 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk) {
         });
         if (z >= z1) break;
     }
+
+    // Fused injection: the workgroup whose tile holds a node adds its
+    // increment once the whole tile is stored.
+    if constexpr (MODE == kStepPlain) {
+        const int xb = (int)bx * kTileX;
+        auto in_tile = [&](int j) {
+            const int zj = fs.inj_zyx[3 * j], yj = fs.inj_zyx[3 * j + 1], xj = fs.inj_zyx[3 * j + 2];
+            return zj >= z0 && zj < z1 && yj >= yb && yj < yb + TY && xj >= xb && xj < xb + kTileX;
+        };
+        bool wg_inj = false;
+        for (int j = 0; j < fs.inj.nrows; ++j) wg_inj = wg_inj || in_tile(j);   // uniform over the workgroup
+        if (wg_inj) {
+            tile_stores_visible();
+            const int j = ty * kTileX + tx;
+            if (j < fs.inj.nrows && in_tile(j)) inj_apply(fs.inj, j);
+        }
+    }
 }
 
 struct Geo2 {
     int32_t nz, nx;
     int64_t sz, origin, total;
+    uint32_t gy;                 // block rows of the tile grid; rows past it sample
 };
 
 // 2-D: block = 64 x NW threads; wave w streams z planes [zw, zw + zchunk).
 template <int M, int NW, int MODE>
 __global__ void __launch_bounds__(kTileX * NW)
-step2d(StepArgs a, StencilCoef k, Geo2 g, int zchunk) {
+step2d(StepArgs a, StencilCoef k, Geo2 g, int zchunk, FusedSparse fs) {
     constexpr int LW = kTileX + 2 * M;
     constexpr int NQ = 2 * M + 1;
     __shared__ float lds[2][NW][LW];
+
+    if (blockIdx.y >= g.gy) {                      // a sampling workgroup
+        const int64_t blk = (int64_t)(blockIdx.y - g.gy) * gridDim.x + blockIdx.x;
+        fused_sample(fs.smp, blk * (kTileX * NW) + threadIdx.y * kTileX + threadIdx.x);
+        return;
+    }
 
     const int tx = threadIdx.x;
     const int w = threadIdx.y;
@@ -356,6 +418,7 @@ step2d(StepArgs a, StencilCoef k, Geo2 g, int zchunk) {
     const int hlx = hl ? tx : (tx + 2 * M);
     const uint32_t o_hx = ((hl || hr) && hx < g.nx + M) ? (uint32_t)(hx + M) * 4u : kOob;
     const float exv = xin ? a.eta_x[x] : 0.f;
+
 
     float q[NQ];
 #pragma unroll
@@ -404,6 +467,23 @@ step2d(StepArgs a, StencilCoef k, Geo2 g, int zchunk) {
             if (MODE == kStepSaveT) bstore<AWE_CPOL_STREAM>(r_gr, t, o_in, soff(z));
         }
     }
+
+    // fused injection (see step3d): the block covers columns [xb, xb + 64)
+    // and planes [zb, zb + NW * zchunk)
+    if constexpr (MODE == kStepPlain) {
+        const int xb = (int)blockIdx.x * kTileX, zb = (int)blockIdx.y * NW * zchunk;
+        auto in_tile = [&](int j) {
+            const int zj = fs.inj_zyx[3 * j], xj = fs.inj_zyx[3 * j + 2];
+            return zj >= zb && zj < zb + NW * zchunk && xj >= xb && xj < xb + kTileX;
+        };
+        bool wg_inj = false;
+        for (int j = 0; j < fs.inj.nrows; ++j) wg_inj = wg_inj || in_tile(j);   // uniform over the block
+        if (wg_inj) {
+            tile_stores_visible();
+            const int j = w * kTileX + tx;
+            if (j < fs.inj.nrows && in_tile(j)) inj_apply(fs.inj, j);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -411,33 +491,39 @@ step2d(StepArgs a, StencilCoef k, Geo2 g, int zchunk) {
 // 3-D configurations: (BY, RY) -> workgroup 64 x BY threads, tile 64 x BY*RY.
 // 2-D configurations: NW waves per workgroup.
 // ---------------------------------------------------------------------------
+// Workgroups that sample `npts` points, `per` threads each.
+inline uint32_t sample_groups(int32_t npts, int per) { return npts > 0 ? (uint32_t)((npts + per - 1) / per) : 0u; }
+
 template <int M, int MODE>
-hipError_t launch3(int cfg, const Layout& L, const StencilCoef& k, const StepArgs& a, int zchunk, hipStream_t s) {
+hipError_t launch3(int cfg, const Layout& L, const StencilCoef& k, const StepArgs& a, int zchunk, hipStream_t s,
+                   const FusedSparse& fs) {
     const int ty = tile_rows(3, cfg);
-    Geo3 g{(int32_t)L.n[0], (int32_t)L.n[1], (int32_t)L.n[2], L.sy, L.sz, L.origin, 0, 0, 0, L.total};
+    Geo3 g{(int32_t)L.n[0], (int32_t)L.n[1], (int32_t)L.n[2], L.sy, L.sz, L.origin, 0, 0, 0, 0, L.total};
     g.gx = (uint32_t)((L.n[2] + kTileX - 1) / kTileX);
     g.gy = (uint32_t)((L.n[1] + ty - 1) / ty);
     const uint32_t gz = (uint32_t)((L.n[0] + zchunk - 1) / zchunk);
     g.ntiles = g.gx * g.gy * gz;
-    const dim3 grid((g.ntiles + kXcds - 1) / kXcds * kXcds);   // a multiple of the XCD count
+    g.ngrid = (g.ntiles + kXcds - 1) / kXcds * kXcds;          // a multiple of the XCD count
+    const int by = (MODE == kStepBorn || MODE == kStepSaveT || cfg >= 2) ? 8 : 4;
+    const dim3 grid(g.ngrid + sample_groups(fs.smp.npts, kTileX * by));
     if constexpr (MODE == kStepBorn || MODE == kStepSaveT) {
         // linearised modelling uses one shape (cfg 3) to bound the number of kernels
         if (cfg != 3) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((step3d<M, 8, 2, MODE>), grid, dim3(kTileX, 8), 0, s, a, k, g, zchunk);
+        hipLaunchKernelGGL((step3d<M, 8, 2, MODE>), grid, dim3(kTileX, 8), 0, s, a, k, g, zchunk, fs);
         return hipGetLastError();
     } else {
         switch (cfg) {
             case 0:     // 64 x 16 tile, 256 threads, 4 rows per thread
-                hipLaunchKernelGGL((step3d<M, 4, 4, MODE>), grid, dim3(kTileX, 4), 0, s, a, k, g, zchunk);
+                hipLaunchKernelGGL((step3d<M, 4, 4, MODE>), grid, dim3(kTileX, 4), 0, s, a, k, g, zchunk, fs);
                 break;
             case 1:     // 64 x 8 tile, 256 threads, 2 rows per thread
-                hipLaunchKernelGGL((step3d<M, 4, 2, MODE>), grid, dim3(kTileX, 4), 0, s, a, k, g, zchunk);
+                hipLaunchKernelGGL((step3d<M, 4, 2, MODE>), grid, dim3(kTileX, 4), 0, s, a, k, g, zchunk, fs);
                 break;
             case 2:     // 64 x 32 tile, 512 threads, 4 rows per thread
-                hipLaunchKernelGGL((step3d<M, 8, 4, MODE>), grid, dim3(kTileX, 8), 0, s, a, k, g, zchunk);
+                hipLaunchKernelGGL((step3d<M, 8, 4, MODE>), grid, dim3(kTileX, 8), 0, s, a, k, g, zchunk, fs);
                 break;
             default:    // 64 x 16 tile, 512 threads, 2 rows per thread
-                hipLaunchKernelGGL((step3d<M, 8, 2, MODE>), grid, dim3(kTileX, 8), 0, s, a, k, g, zchunk);
+                hipLaunchKernelGGL((step3d<M, 8, 2, MODE>), grid, dim3(kTileX, 8), 0, s, a, k, g, zchunk, fs);
                 break;
         }
         return hipGetLastError();
@@ -445,20 +531,23 @@ hipError_t launch3(int cfg, const Layout& L, const StencilCoef& k, const StepArg
 }
 
 template <int M, int MODE>
-hipError_t launch2(int cfg, const Layout& L, const StencilCoef& k, const StepArgs& a, int zchunk, hipStream_t s) {
-    Geo2 g{(int32_t)L.n[0], (int32_t)L.n[2], L.sz, L.origin, L.total};
+hipError_t launch2(int cfg, const Layout& L, const StencilCoef& k, const StepArgs& a, int zchunk, hipStream_t s,
+                   const FusedSparse& fs) {
+    Geo2 g{(int32_t)L.n[0], (int32_t)L.n[2], L.sz, L.origin, L.total, 0};
     const unsigned gx = (unsigned)((L.n[2] + kTileX - 1) / kTileX);
-    const int nw = (cfg == 0) ? 4 : 1;
+    const int nw = (MODE == kStepBorn || MODE == kStepSaveT || cfg == 0) ? 4 : 1;
     const int64_t per_block = (int64_t)nw * zchunk;
-    dim3 grid(gx, (unsigned)((L.n[0] + per_block - 1) / per_block));
+    g.gy = (uint32_t)((L.n[0] + per_block - 1) / per_block);
+    const uint32_t sg = sample_groups(fs.smp.npts, kTileX * nw);
+    dim3 grid(gx, g.gy + (sg + gx - 1) / gx);   // sampling rows after the tile rows
     if constexpr (MODE == kStepBorn || MODE == kStepSaveT) {
         if (cfg != 0) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((step2d<M, 4, MODE>), grid, dim3(kTileX, 4), 0, s, a, k, g, zchunk);
+        hipLaunchKernelGGL((step2d<M, 4, MODE>), grid, dim3(kTileX, 4), 0, s, a, k, g, zchunk, fs);
     } else {
         if (nw == 4)
-            hipLaunchKernelGGL((step2d<M, 4, MODE>), grid, dim3(kTileX, 4), 0, s, a, k, g, zchunk);
+            hipLaunchKernelGGL((step2d<M, 4, MODE>), grid, dim3(kTileX, 4), 0, s, a, k, g, zchunk, fs);
         else
-            hipLaunchKernelGGL((step2d<M, 1, MODE>), grid, dim3(kTileX, 1), 0, s, a, k, g, zchunk);
+            hipLaunchKernelGGL((step2d<M, 1, MODE>), grid, dim3(kTileX, 1), 0, s, a, k, g, zchunk, fs);
     }
     return hipGetLastError();
 }
@@ -466,13 +555,13 @@ hipError_t launch2(int cfg, const Layout& L, const StencilCoef& k, const StepArg
 // every mode for one half-width M
 template <int M>
 hipError_t launch_m(const Layout& L, const StencilCoef& k, const StepArgs& a, int mode, int cfg, int zchunk,
-                    hipStream_t s) {
+                    hipStream_t s, const FusedSparse& fs) {
     const bool d3 = L.ndim == 3;
     switch (mode) {
-        case kStepPlain: return d3 ? launch3<M, kStepPlain>(cfg, L, k, a, zchunk, s) : launch2<M, kStepPlain>(cfg, L, k, a, zchunk, s);
-        case kStepImaging: return d3 ? launch3<M, kStepImaging>(cfg, L, k, a, zchunk, s) : launch2<M, kStepImaging>(cfg, L, k, a, zchunk, s);
-        case kStepBorn: return d3 ? launch3<M, kStepBorn>(cfg, L, k, a, zchunk, s) : launch2<M, kStepBorn>(cfg, L, k, a, zchunk, s);
-        case kStepSaveT: return d3 ? launch3<M, kStepSaveT>(cfg, L, k, a, zchunk, s) : launch2<M, kStepSaveT>(cfg, L, k, a, zchunk, s);
+        case kStepPlain: return d3 ? launch3<M, kStepPlain>(cfg, L, k, a, zchunk, s, fs) : launch2<M, kStepPlain>(cfg, L, k, a, zchunk, s, fs);
+        case kStepImaging: return d3 ? launch3<M, kStepImaging>(cfg, L, k, a, zchunk, s, fs) : launch2<M, kStepImaging>(cfg, L, k, a, zchunk, s, fs);
+        case kStepBorn: return d3 ? launch3<M, kStepBorn>(cfg, L, k, a, zchunk, s, fs) : launch2<M, kStepBorn>(cfg, L, k, a, zchunk, s, fs);
+        case kStepSaveT: return d3 ? launch3<M, kStepSaveT>(cfg, L, k, a, zchunk, s, fs) : launch2<M, kStepSaveT>(cfg, L, k, a, zchunk, s, fs);
         default: return hipErrorInvalidValue;
     }
 }

@@ -225,3 +225,28 @@ def test_nearby_3d_sizes_reuse_a_tuned_shape(monkeypatch):
         plan.close()
     log(f"tuned {outs[0]}, reused {outs[1]}")
     assert outs[0] == outs[1]
+
+
+@pytest.mark.parametrize("kind", ["2d", "3d"])
+def test_fused_point_operators_bitwise(monkeypatch, kind):
+    # A plain step with few source nodes injects and samples inside the
+    # stencil launch; it must give exactly what the separate point-operator
+    # launch gives.  The source sits on an x-tile seam, a y-tile seam (3-D)
+    # and a z-chunk seam of the forced shapes, so its nodes belong to
+    # different workgroups.
+    if kind == "3d":
+        shot = small_3d_shot(330, 8, nt=50)      # padded 52 x 58 x 102, nbl 6
+        h = shot.spacing
+        shot.src_coords = np.array([[(6.5 - 6) * h[0], (15.5 - 6) * h[1], (63.5 - 6) * h[2]]])
+        cfgs = ("3,7", "0,7", "1,16")
+    else:
+        shot = small_2d_shot(331, 8, nt=80)      # padded 170 x 190, nbl 10
+        h = shot.spacing
+        shot.src_coords = np.array([[(15.5 - 10) * h[0], (63.5 - 10) * h[1]]])
+        cfgs = ("0,4", "1,16")
+    dt = shot_dt(shot)
+    for cfg in cfgs:
+        fused = _forward_with_env(monkeypatch, shot, dt, {"AWE_TILE": cfg, "AWE_FUSE": None})
+        split = _forward_with_env(monkeypatch, shot, dt, {"AWE_TILE": cfg, "AWE_FUSE": "0"})
+        assert np.any(fused[0] != 0.0)
+        assert np.array_equal(fused[0], split[0]) and np.array_equal(fused[1], split[1]), cfg
