@@ -67,6 +67,7 @@ hipError_t launch_step(const Layout& L, const StencilCoef& k, const StepArgs& a,
                        int tile_cfg, int zchunk, hipStream_t s, const FusedSparse* fs = nullptr);
 int num_tile_cfgs(int ndim);
 int tile_rows(int ndim, int tile_cfg);   // y rows (3-D) or z chunks per block (2-D)
+int tile_cols(int ndim, int tile_cfg);   // x columns per tile (3-D; 64 in 2-D)
 
 // One launch of the off-grid point operators (kernels_aux.hip): injection
 // into one array and sampling of another.  A zero count disables either part.

@@ -410,11 +410,13 @@ constexpr int64_t kTuneMinPoints3 = 4 << 20;
 constexpr int64_t kTuneMinPoints2 = 1 << 16;
 
 // A shape tuned for a grid of the same dimensionality, order and mode with a
-// point count within a factor of two, if there is one: taken instead of
-// timing again (a server meets many nearby sizes).
+// point count within 30%, if there is one: taken instead of timing again (a
+// server meets many nearby sizes).  The window is narrow because the best
+// shape changes where the fields outgrow the 256 MB Infinity Cache (between
+// 336^3 and 380^3 at order 8).
 bool nearby_shape(const TuneKey& key, LaunchShape& out) {
     const double pts = (double)key.n0 * key.n1 * key.n2;
-    double best = 2.0;
+    double best = 1.3;
     bool found = false;
     for (const auto& kv : g_tune_cache) {
         const TuneKey& o = kv.first;
@@ -462,7 +464,7 @@ awe_status Plan::tune(bool img, hipStream_t user_stream) {
     }
     std::vector<LaunchShape> cand;
     if (g.ndim == 3) {
-        for (int cfg : {0, 1, 3})
+        for (int cfg : {0, 1, 3, 4, 5})
             for (int zc : {28, 42, 56, 70, 84}) cand.push_back({cfg, zc});
     } else {
         for (int zc : {4, 8, 16, 32, 64}) cand.push_back({0, zc});
@@ -480,13 +482,14 @@ awe_status Plan::tune(bool img, hipStream_t user_stream) {
                      : StepArgs{w0, w1, w1, coef, d_ez, d_ey, d_ex, nullptr, nullptr};
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
-    // three interleaved rounds; a candidate's time is its fastest round
+    // two interleaved rounds of four timed launches (after one untimed); a
+    // candidate's time is its faster round
     std::vector<float> best_of(cand.size(), 1e30f);
-    for (int round = 0; round < 3 && e == hipSuccess; ++round) {
+    for (int round = 0; round < 2 && e == hipSuccess; ++round) {
         for (size_t i = 0; e == hipSuccess && i < cand.size(); ++i) {
             e = launch_step(L, k, a, img ? kStepImaging : kStepPlain, cand[i].cfg, cand[i].zchunk, s);
             if (e == hipSuccess) e = hipEventRecord(e0, s);
-            for (int w = 0; w < 5 && e == hipSuccess; ++w) e = launch_step(L, k, a, img ? kStepImaging : kStepPlain, cand[i].cfg, cand[i].zchunk, s);
+            for (int w = 0; w < 4 && e == hipSuccess; ++w) e = launch_step(L, k, a, img ? kStepImaging : kStepPlain, cand[i].cfg, cand[i].zchunk, s);
             if (e == hipSuccess) e = hipEventRecord(e1, s);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0.f;

@@ -10,15 +10,19 @@ hipError_t launch_step_lo(const Layout& L, const StencilCoef& k, const StepArgs&
 hipError_t launch_step_hi(const Layout& L, const StencilCoef& k, const StepArgs& a, int mode, int cfg, int zchunk,
                           hipStream_t s, const FusedSparse& fs);
 
-int num_tile_cfgs(int ndim) { return ndim == 3 ? 4 : 2; }
+int num_tile_cfgs(int ndim) { return ndim == 3 ? 6 : 2; }
 
+// 3-D workgroup shapes: cfg 0..5 = 64x16, 64x8, 64x32, 64x16, 128x8, 128x16
+// points (x by y) per tile; 2-D: cfg 0 = 4 waves, 1 = 1 wave per block.
 int tile_rows(int ndim, int cfg) {
     if (ndim == 3) {
-        static const int rows[4] = {16, 8, 32, 16};
-        return rows[cfg & 3];
+        static const int rows[6] = {16, 8, 32, 16, 8, 16};
+        return rows[(cfg >= 0 && cfg < 6) ? cfg : 3];
     }
     return cfg == 0 ? 4 : 1;
 }
+
+int tile_cols(int ndim, int cfg) { return (ndim == 3 && (cfg == 4 || cfg == 5)) ? 128 : 64; }
 
 hipError_t launch_step(const Layout& L, const StencilCoef& k, const StepArgs& a, int mode, int cfg, int zchunk,
                        hipStream_t s, const FusedSparse* fused) {

@@ -150,15 +150,16 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, float v, uint32
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, CPOL);
 }
 
-template <int M, int BY, int RY, int MODE>
-__global__ void __launch_bounds__(kTileX * BY)
+template <int M, int BX, int BY, int RY, int MODE>
+__global__ void __launch_bounds__(kTileX * BX * BY)
 step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk, FusedSparse fs) {
+    constexpr int TX = kTileX * BX;               // tile width: BX wavefronts side by side
     constexpr int TY = BY * RY;
-    // LDS row pitch of 128 dwords (two 64-dword units): every y-neighbour pair
-    // (y-k, y+k) is then one ds_read2st64 with immediate offsets, instead of
-    // an address computation per pair at 80-dword pitches
-    constexpr int LW = 128;
-    static_assert(kTileX + 2 * M <= LW, "halo wider than the LDS row");
+    // LDS row pitch, a multiple of 64 dwords (128 for one wavefront): every
+    // y-neighbour pair (y-k, y+k) is then one ds_read2st64 with immediate
+    // offsets, instead of an address computation per pair
+    constexpr int LW = BX == 1 ? 128 : 64 * ((TX + 2 * M + 63) / 64);
+    static_assert(TX + 2 * M <= LW, "halo wider than the LDS row");
     constexpr int LH = TY + 2 * M;
     constexpr int NQ = 2 * M + 1;
     constexpr int NH = (2 * M + BY - 1) / BY;     // y-halo rows per thread row
@@ -166,16 +167,20 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk, FusedSparse fs) {
     __shared__ float lds[2][LH][LW];
 
     if (blockIdx.x >= g.ngrid) {                   // a sampling workgroup
-        fused_sample(fs.smp, (int64_t)(blockIdx.x - g.ngrid) * (kTileX * BY) + threadIdx.y * kTileX + threadIdx.x);
+        fused_sample(fs.smp, (int64_t)(blockIdx.x - g.ngrid) * (kTileX * BX * BY) + threadIdx.y * kTileX + threadIdx.x);
         return;
     }
     uint32_t bx, by, bz;
     if (!xcd_tile(g, bx, by, bz)) return;          // uniform over the workgroup
     const int tx = threadIdx.x;
-    // A thread row (64 lanes) is one wavefront, so everything indexed by ty
-    // is wave-uniform and lives in scalar registers.
-    const int ty = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
-    const int x = bx * kTileX + tx;
+    // Each wavefront (64 lanes) owns 64 columns of RY rows: wave wv is column
+    // block wx and thread row ty, so everything indexed by them is
+    // wave-uniform and lives in scalar registers.
+    const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
+    const int wx = wv % BX;
+    const int ty = wv / BX;
+    const int lxb = wx * kTileX;                   // tile-local first column of this wave
+    const int x = bx * TX + lxb + tx;
     const int yb = by * TY;
     const int y0 = yb + ty * RY;
     const int z0 = bz * zchunk;
@@ -214,13 +219,14 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk, FusedSparse fs) {
     uint32_t v_str[RY];
 #pragma unroll
     for (int r = 0; r < RY; ++r) v_str[r] = (y0 + r < g.ny) ? v_st : kOob;
-    // x halo: lanes tx < M load the left columns, lanes tx >= 64-M the right ones.
-    const bool hl = tx < M;
-    const bool hr = tx >= kTileX - M;
-    const int hlx = hl ? tx : (tx + 2 * M);        // LDS column of the halo value
+    // x halo: lanes tx < M of the first wave column load the left columns,
+    // lanes tx >= 64-M of the last the right ones.
+    const bool hl = wx == 0 && tx < M;
+    const bool hr = wx == BX - 1 && tx >= kTileX - M;
+    const int hlx = hl ? tx : (lxb + tx + 2 * M);  // LDS column of the halo value
     const uint32_t v_hx = (hl || hr) ? colb(hl ? x - M : x + M) : kOob;
-    // y halo: 2M rows (M above, M below the tile), 64 columns; thread row ty
-    // loads halo rows h = ty, ty + BY, ... < 2M.
+    // y halo: 2M rows (M above, M below the tile); thread row ty loads halo
+    // rows h = ty, ty + BY, ... < 2M in its wave's 64 columns.
     int hyrow[NH];
     uint32_t s_hy[NH];
 #pragma unroll
@@ -283,12 +289,12 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk, FusedSparse fs) {
         // stage plane z in LDS
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-            lds[b][M + ty * RY + r][M + tx] = Q(r, M);
+            lds[b][M + ty * RY + r][M + lxb + tx] = Q(r, M);
             if (hl || hr) lds[b][M + ty * RY + r][hlx] = hxv[r];
         }
 #pragma unroll
         for (int i = 0; i < NH; ++i)
-            if (kHyFull || ty + i * BY < 2 * M) lds[b][hyrow[i]][M + tx] = hyv[i];
+            if (kHyFull || ty + i * BY < 2 * M) lds[b][hyrow[i]][M + lxb + tx] = hyv[i];
 
         float p[RY], c[RY], s[RY], gg[RY];
 #pragma unroll
@@ -306,7 +312,7 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk, FusedSparse fs) {
         // (the empty asm emits nothing): every neighbour is then an immediate
         // offset from them (x: 0..2M dwords, y: multiples of LW), so each pair
         // of reads is one ds_read2 / ds_read2st64 with no address arithmetic.
-        int lofs = (b * LH + ty * RY) * LW + tx + M;   // (row ly - M, column lx)
+        int lofs = (b * LH + ty * RY) * LW + lxb + tx + M;   // (row ly - M, column lx)
         asm volatile("" : "+v"(lofs));
         int lrow[RY];                                  // (row ly, column lx - M)
 #pragma unroll
@@ -352,16 +358,16 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk, FusedSparse fs) {
     // Fused injection: the workgroup whose tile holds a node adds its
     // increment once the whole tile is stored.
     if constexpr (MODE == kStepPlain) {
-        const int xb = (int)bx * kTileX;
+        const int xb = (int)bx * TX;
         auto in_tile = [&](int j) {
             const int zj = fs.inj_zyx[3 * j], yj = fs.inj_zyx[3 * j + 1], xj = fs.inj_zyx[3 * j + 2];
-            return zj >= z0 && zj < z1 && yj >= yb && yj < yb + TY && xj >= xb && xj < xb + kTileX;
+            return zj >= z0 && zj < z1 && yj >= yb && yj < yb + TY && xj >= xb && xj < xb + TX;
         };
         bool wg_inj = false;
         for (int j = 0; j < fs.inj.nrows; ++j) wg_inj = wg_inj || in_tile(j);   // uniform over the workgroup
         if (wg_inj) {
             tile_stores_visible();
-            const int j = ty * kTileX + tx;
+            const int j = wv * kTileX + tx;
             if (j < fs.inj.nrows && in_tile(j)) inj_apply(fs.inj, j);
         }
     }
@@ -497,37 +503,45 @@ inline uint32_t sample_groups(int32_t npts, int per) { return npts > 0 ? (uint32
 template <int M, int MODE>
 hipError_t launch3(int cfg, const Layout& L, const StencilCoef& k, const StepArgs& a, int zchunk, hipStream_t s,
                    const FusedSparse& fs) {
-    const int ty = tile_rows(3, cfg);
+    if constexpr (MODE == kStepBorn || MODE == kStepSaveT) {
+        // linearised modelling uses one shape (cfg 3) to bound the number of kernels
+        if (cfg != 3) return hipErrorInvalidValue;
+    }
+    const int ty = tile_rows(3, cfg), tcols = tile_cols(3, cfg);
     Geo3 g{(int32_t)L.n[0], (int32_t)L.n[1], (int32_t)L.n[2], L.sy, L.sz, L.origin, 0, 0, 0, 0, L.total};
-    g.gx = (uint32_t)((L.n[2] + kTileX - 1) / kTileX);
+    g.gx = (uint32_t)((L.n[2] + tcols - 1) / tcols);
     g.gy = (uint32_t)((L.n[1] + ty - 1) / ty);
     const uint32_t gz = (uint32_t)((L.n[0] + zchunk - 1) / zchunk);
     g.ntiles = g.gx * g.gy * gz;
     g.ngrid = (g.ntiles + kXcds - 1) / kXcds * kXcds;          // a multiple of the XCD count
-    const int by = (MODE == kStepBorn || MODE == kStepSaveT || cfg >= 2) ? 8 : 4;
-    const dim3 grid(g.ngrid + sample_groups(fs.smp.npts, kTileX * by));
+    const int waves = (cfg == 0 || cfg == 1) ? 4 : 8;
+    const dim3 grid(g.ngrid + sample_groups(fs.smp.npts, kTileX * waves));
+    const dim3 block(kTileX, waves);
     if constexpr (MODE == kStepBorn || MODE == kStepSaveT) {
-        // linearised modelling uses one shape (cfg 3) to bound the number of kernels
-        if (cfg != 3) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((step3d<M, 8, 2, MODE>), grid, dim3(kTileX, 8), 0, s, a, k, g, zchunk, fs);
-        return hipGetLastError();
+        hipLaunchKernelGGL((step3d<M, 1, 8, 2, MODE>), grid, block, 0, s, a, k, g, zchunk, fs);
     } else {
         switch (cfg) {
             case 0:     // 64 x 16 tile, 256 threads, 4 rows per thread
-                hipLaunchKernelGGL((step3d<M, 4, 4, MODE>), grid, dim3(kTileX, 4), 0, s, a, k, g, zchunk, fs);
+                hipLaunchKernelGGL((step3d<M, 1, 4, 4, MODE>), grid, block, 0, s, a, k, g, zchunk, fs);
                 break;
             case 1:     // 64 x 8 tile, 256 threads, 2 rows per thread
-                hipLaunchKernelGGL((step3d<M, 4, 2, MODE>), grid, dim3(kTileX, 4), 0, s, a, k, g, zchunk, fs);
+                hipLaunchKernelGGL((step3d<M, 1, 4, 2, MODE>), grid, block, 0, s, a, k, g, zchunk, fs);
                 break;
             case 2:     // 64 x 32 tile, 512 threads, 4 rows per thread
-                hipLaunchKernelGGL((step3d<M, 8, 4, MODE>), grid, dim3(kTileX, 8), 0, s, a, k, g, zchunk, fs);
+                hipLaunchKernelGGL((step3d<M, 1, 8, 4, MODE>), grid, block, 0, s, a, k, g, zchunk, fs);
+                break;
+            case 4:     // 128 x 8 tile, 512 threads, 2 rows per thread
+                hipLaunchKernelGGL((step3d<M, 2, 4, 2, MODE>), grid, block, 0, s, a, k, g, zchunk, fs);
+                break;
+            case 5:     // 128 x 16 tile, 512 threads, 4 rows per thread
+                hipLaunchKernelGGL((step3d<M, 2, 4, 4, MODE>), grid, block, 0, s, a, k, g, zchunk, fs);
                 break;
             default:    // 64 x 16 tile, 512 threads, 2 rows per thread
-                hipLaunchKernelGGL((step3d<M, 8, 2, MODE>), grid, dim3(kTileX, 8), 0, s, a, k, g, zchunk, fs);
+                hipLaunchKernelGGL((step3d<M, 1, 8, 2, MODE>), grid, block, 0, s, a, k, g, zchunk, fs);
                 break;
         }
-        return hipGetLastError();
     }
+    return hipGetLastError();
 }
 
 template <int M, int MODE>
