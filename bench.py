@@ -42,19 +42,29 @@ PROFILE = os.path.join(ROOT, "profiles", "step3d_o8_336cube_forward.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_1608_08658_amd", "csrc", "stencil_impl.hpp")
 
 
+def kernel_source_digest(path=KERNEL_SRC):
+    """sha256 of the stencil source without its comments and blank lines:
+    recorded counters stay valid across edits of the comments, not of the
+    code."""
+    import hashlib
+    import re
+    text = re.sub(r"/\*.*?\*/", "", open(path).read(), flags=re.S)
+    lines = [re.sub(r"//.*$", "", line).rstrip() for line in text.splitlines()]
+    return hashlib.sha256("\n".join(line for line in lines if line.strip()).encode()).hexdigest()
+
+
 def profiled_traffic(shape):
     """HBM bytes per stencil launch from the committed rocprofv3 counter
-    summary, or None when the kernel source or launch shape has changed
-    since the counters were taken."""
-    import hashlib
+    summary, or None when the kernel code or launch shape has changed since
+    the counters were taken."""
     try:
         facts = {}
         for line in open(PROFILE):
             if ":" in line and line.startswith("    ") and not line.strip().startswith(("cd ", "|")):
                 k, v = line.strip().split(":", 1)
-                facts[k.strip()] = v.strip()
-        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-        if facts.get("source_sha256") != sha or facts.get("launch_shape") != f"{shape[0]},{shape[1]}":
+                facts[k.strip()] = v.split()[0] if v.split() else ""
+        sha = kernel_source_digest()
+        if facts.get("source_digest") != sha or facts.get("launch_shape") != f"{shape[0]},{shape[1]}":
             return None
         return float(facts["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):

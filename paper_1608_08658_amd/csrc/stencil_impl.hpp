@@ -20,20 +20,23 @@
 // difference of mu avoids the cancellation of three nearly equal FP32 values.
 //
 // Memory access plan (HBM-bound: 16 B per point forward, 28 B with imaging):
-//   * a workgroup owns a 64 (x, one wavefront wide) x TY (y) column of the grid
-//     and streams through a chunk of z planes;
+//   * a workgroup owns a TX (x: one or two wavefronts of 64 points) x TY (y)
+//     column of the grid and streams through a chunk of z planes;
 //   * each thread keeps its points' z-neighbourhood (2M+1 planes) in registers,
 //     so every value of uc is fetched from HBM once per z-chunk;
 //   * the current plane, with an M-wide x/y halo, is staged in LDS (double
 //     buffered, one barrier per plane) for the x and y derivatives; the halo
-//     cells are re-read from L2 / the Infinity Cache, not HBM;
+//     cells are re-read from L2 / the Infinity Cache;
 //   * the loads for plane z+1 are issued before the barrier of plane z so their
 //     latency hides behind the arithmetic of plane z;
 //   * each thread owns RY consecutive y rows, so y-neighbours inside its own
 //     rows come from registers;
-//   * a thread row is one wavefront, so row indices and row offsets are
-//     wave-uniform (scalar registers): the vector registers hold the queue,
-//     the prefetched values and one column offset per lane.
+//   * a wavefront owns 64 columns of one thread row, so row indices and row
+//     offsets are wave-uniform (scalar registers): the vector registers hold
+//     the queue, the prefetched values and one column offset per lane.
+// A plain step may also carry its time step's point operators (FusedSparse):
+// workgroups appended to the tile grid sample the input, and the workgroup
+// whose tile holds a source node adds the injection after its sweep.
 // 2-D uses the same scheme with a 64-point x row in LDS and no y axis.
 #pragma once
 
