@@ -134,3 +134,26 @@ def test_binomial_gradient_crop_order16_2000_steps():
     assert np.array_equal(host(g0), host(g1))
     assert b1 < b0
     plan.close()
+
+
+@pytest.mark.parametrize("nt", [1, 2, 3])
+def test_binomial_tiny_step_counts(nt):
+    # no step, one step, two steps: the schedule degenerates, the gradient
+    # (zero for nt = 1) and F^T still equal the periodic ones bit for bit
+    shot = small_3d_shot(750 + nt, 4, nt=nt)
+    dt = shot_dt(shot)
+    w = (shot.wavelet(dt) * 1e3).astype(np.float32)
+    rng = np.random.default_rng(nt)
+    y = rng.standard_normal((nt, len(shot.rec_coords))).astype(np.float32)
+    plan = gpu_plan(shot, dt)
+    plan.set_model(dev(shot.m))
+    tr0 = host(plan.forward(dev(w), ckpt_every=1))
+    sa0, g0 = plan.adjoint(dev(y), want_src_adj=True, want_grad=True)
+    sa0, g0 = host(sa0), host(g0)
+    for s in (0, 1, 5):
+        tr = host(plan.forward(dev(w), snapshots=s))
+        sa, g = plan.adjoint(dev(y), want_src_adj=True, want_grad=True)
+        assert np.array_equal(tr, tr0) and np.array_equal(host(sa), sa0) and np.array_equal(host(g), g0), s
+    if nt == 1:
+        assert np.all(g0 == 0.0)
+    plan.close()
