@@ -287,6 +287,40 @@ def bench_served_gradient(torch, awe, synth, n=300, nt=1500, nshots=32):
             "total_misfit": loss_sum, "gradient_finite": bool(torch.isfinite(total).all().item())}
 
 
+def bench_born(torch, awe, synth, n=256, nt=1000):
+    """Linearised (Born) modelling J dm on the forward workload's grid: the
+    background and the scattered field advance together, 44 algorithmic
+    bytes per point-step (background: read u[n], u[n-1], C, write u[n+1]
+    and its second time difference t; scattered: read du[n], du[n-1], C, dm,
+    t, write du[n+1])."""
+    shot = synth.config_3d_forward(n=n, nt=nt)
+    dt = shot.dt_factor * awe.dt_max(3, shot.order, shot.spacing, shot.vmax)
+    plan = awe.Plan(shape=shot.shape, spacing=shot.spacing, space_order=shot.order, nbl=shot.nbl, dt=dt, nt=shot.nt,
+                    src_coords=shot.src_coords, rec_coords=shot.rec_coords, damp_power=shot.damp_power,
+                    damp_R=shot.damp_R, damp_vref=shot.damp_vref)
+    plan.set_model(torch.tensor(shot.m, dtype=torch.float32, device="cuda"))
+    w = torch.tensor(shot.wavelet(dt), dtype=torch.float32, device="cuda")
+    rng = np.random.default_rng(9)
+    dm = torch.tensor((0.05 * shot.m * synth.random_state(rng, shot.shape, 4.0)).astype(np.float32), device="cuda")
+    plan.born(w, dm)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    tr = plan.born(w, dm)
+    ev[1].record()
+    torch.cuda.synchronize()
+    t = ev[0].elapsed_time(ev[1]) / 1e3
+    npad = int(np.prod(plan.padded))
+    finite = bool(torch.isfinite(tr).all().item())
+    plan.close()
+    gbs = 44.0 * npad * (shot.nt - 1) / t / 1e9
+    log(f"Born modelling: {t * 1e3:.1f} ms, {npad * (shot.nt - 1) / t / 1e9:.1f} G updates/s of the pair, "
+        f"{gbs:.0f} GB/s algorithmic ({100 * gbs / HBM_PEAK_GBS:.1f}%)")
+    return {"workload": f"J dm on the {n}^3 order-8 forward workload ({'x'.join(map(str, shot.shape))} physical, "
+                        f"{shot.nt} samples, {len(shot.rec_coords)} receivers), smooth 5% dm",
+            "born_s": t, "pair_updates_per_s": npad * (shot.nt - 1) / t, "bytes_per_update": 44.0,
+            "algorithmic_GBps": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS, "finite": finite}
+
+
 def bench_paper_example(torch, awe, synth):
     """The paper's 3-D run (Sec. V.D): 281 x 281 x 150 computed points,
     h = 15 m, order 14, 10 Hz Ricker, 1 s modelled, synthetic layered model."""
@@ -329,6 +363,7 @@ def main():
     ap.add_argument("--binomial-snapshots", type=int, default=20,
                     help="stored states of the binomial-checkpointing gradient (-1 = skip it)")
     ap.add_argument("--paper-example", type=int, default=1, help="run the paper's 3-D example workload (0 = skip)")
+    ap.add_argument("--born", type=int, default=1, help="time Born modelling on the forward grid (0 = skip)")
     ap.add_argument("--serve-requests", type=int, default=64, help="requests in the serving run (0 = skip)")
     ap.add_argument("--serve-scale", type=float, default=0.5, help="size/step scale of the serving mix")
     ap.add_argument("--served-gradient-shots", type=int, default=0,
@@ -426,6 +461,11 @@ def main():
         log("paper example workload ...")
         paper = bench_paper_example(torch, awe, synth)
 
+    born = None
+    if args.born:
+        log("Born modelling ...")
+        born = bench_born(torch, awe, synth, n=args.n, nt=args.nt)
+
     serve = None
     if args.serve_requests > 0:
         log("serving workload ...")
@@ -476,6 +516,7 @@ def main():
         "cpu_baseline": base,
         "gradient": grad,
         "paper_example": paper,
+        "born": born,
         "serving": serve,
         "served_gradients": shots,
         "setup_s": round(setup_s, 3),

@@ -95,12 +95,13 @@ struct SampleOp {
 };
 hipError_t launch_sparse(const InjectOp& a, const SampleOp& b, hipStream_t s);
 
-// The point operators of one plain time step carried out by the stencil
-// launch itself: extra workgroups past the tile grid sample the step's input
-// u[n] (which the launch only reads), and the few workgroups whose tile holds
-// an injection node add its increment to u[n+1] before storing it, with the
-// same arithmetic as launch_sparse (u[n+1] is rounded first, then the
-// increment added).  Injection is fused only for at most kFuseMaxNodes nodes.
+// The point operators of one time step carried out by the stencil launch
+// itself: extra workgroups past the tile grid sample the step's input (which
+// the launch only reads), and in plain and save-t steps the few workgroups
+// whose tile holds an injection node add its increment to the output (and to
+// t in save-t) after their sweep, with the same arithmetic as launch_sparse
+// (the stored value first, then the increment added).  Injection is fused
+// only for at most kFuseMaxNodes nodes.
 constexpr int kFuseMaxNodes = 8;
 struct FusedSparse {
     InjectOp inj;                      // inj.field is the step's output; nrows <= kFuseMaxNodes

@@ -784,12 +784,23 @@ awe_status Plan::born(const float* wavelet, const float* dm_phys, float* traces,
     for (int n = 0; n + 1 < g.nt; ++n) {
         float* dst = const_cast<float*>(prev);          // in place over u[n-1]
         StepArgs a{cur, prev, dst, coef, d_ez, d_ey, d_ex, nullptr, b_t};
-        AWE_HIP(launch_step(L, k, a, kStepSaveT, cfg, zc, s));
-        // the source into u[n+1] (and t); trace row n samples du[n]
-        AWE_HIP(launch_sparse(src_op(dst, g.nsrc ? wavelet + (size_t)n * g.nsrc : nullptr, b_t),
-                              rec_op(tr ? tr + (size_t)n * g.nrec : nullptr, dcur), s));
         StepArgs b{dcur, dprev, dprev, coef, d_ez, d_ey, d_ex, b_dm, b_t};
-        AWE_HIP(launch_step(L, k, b, kStepBorn, cfg, zc, s));
+        // the source into u[n+1] (and t); trace row n samples du[n]
+        const InjectOp inj = src_op(dst, g.nsrc ? wavelet + (size_t)n * g.nsrc : nullptr, b_t);
+        const SampleOp smp = rec_op(tr ? tr + (size_t)n * g.nrec : nullptr, dcur);
+        if (fuse_sparse && inj.nrows <= kFuseMaxNodes && (inj.nrows == 0 || src_zyx)) {
+            // two launches per step: the background step injects, the scattered step samples
+            FusedSparse fa, fb;
+            fa.inj = inj;
+            fa.inj_zyx = src_zyx;
+            fb.smp = smp;
+            AWE_HIP(launch_step(L, k, a, kStepSaveT, cfg, zc, s, &fa));
+            AWE_HIP(launch_step(L, k, b, kStepBorn, cfg, zc, s, &fb));
+        } else {
+            AWE_HIP(launch_step(L, k, a, kStepSaveT, cfg, zc, s));
+            AWE_HIP(launch_sparse(inj, smp, s));
+            AWE_HIP(launch_step(L, k, b, kStepBorn, cfg, zc, s));
+        }
         prev = cur;
         cur = dst;
         std::swap(dcur, dprev);

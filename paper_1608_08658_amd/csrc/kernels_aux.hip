@@ -36,9 +36,11 @@ sparse_k(InjectOp a, SampleOp b) {
             for (int e = a.rowptr[j]; e < a.rowptr[j + 1]; ++e) s = __builtin_fmaf(a.w[e], a.values[a.pt[e]], s);
             const int64_t i = a.node[j];
             const float cs = s * a.scale;
-            const float inc = a.coef[i] * cs;
             a.field[i] = __builtin_fmaf(a.coef[i], cs, a.field[i]);
-            if (a.grad) a.grad[i] += (a.usnap ? a.usnap[i] : 1.f) * inc;
+            if (a.grad) {
+                a.grad[i] = a.usnap ? __builtin_fmaf(a.usnap[i], a.coef[i] * cs, a.grad[i])   // imaging: g += u inc
+                                    : __builtin_fmaf(a.coef[i], cs, a.grad[i]);               // save-t:  t += inc
+            }
         } else {
             const int64_t r = j - a.nrows;
             float s = 0.f;

@@ -30,12 +30,17 @@ hipError_t launch_step(const Layout& L, const StencilCoef& k, const StepArgs& a,
         return hipErrorInvalidValue;
     const FusedSparse none{};
     const FusedSparse& fs = fused ? *fused : none;
-    // fused point operators: plain steps only, injection into the output,
-    // sampling of the input, at most kFuseMaxNodes injection nodes
-    if (fused && (mode != kStepPlain || fs.inj.nrows > kFuseMaxNodes || fs.inj.nrows < 0 || fs.smp.npts < 0 ||
-                  (fs.inj.nrows > 0 && (fs.inj.field != a.out || !fs.inj_zyx)) ||
-                  (fs.smp.npts > 0 && fs.smp.field != a.uc)))
-        return hipErrorInvalidValue;
+    // fused point operators: sampling of the input (any mode); injection into
+    // the output of a plain step, or of a save-t step together with t (its
+    // second output), at most kFuseMaxNodes nodes
+    if (fused) {
+        const bool inj = fs.inj.nrows > 0;
+        const bool ok_inj = !inj || (fs.inj_zyx && fs.inj.field == a.out && fs.inj.nrows <= kFuseMaxNodes &&
+                                     !fs.inj.usnap &&
+                                     ((mode == kStepPlain && !fs.inj.grad) || (mode == kStepSaveT && fs.inj.grad == a.grad)));
+        const bool ok_smp = fs.smp.npts == 0 || (fs.smp.npts > 0 && fs.smp.field == a.uc);
+        if (!ok_inj || !ok_smp || fs.inj.nrows < 0) return hipErrorInvalidValue;
+    }
     // a workgroup's slab (zchunk + 2M planes) must be addressable with 31-bit
     // byte offsets; tiling never changes results, so shorten the chunk if not
     const int64_t max_planes = 0x7FFFFFF0ll / (4 * L.sz);

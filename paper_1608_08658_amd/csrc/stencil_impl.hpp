@@ -34,9 +34,10 @@
 //   * a wavefront owns 64 columns of one thread row, so row indices and row
 //     offsets are wave-uniform (scalar registers): the vector registers hold
 //     the queue, the prefetched values and one column offset per lane.
-// A plain step may also carry its time step's point operators (FusedSparse):
-// workgroups appended to the tile grid sample the input, and the workgroup
-// whose tile holds a source node adds the injection after its sweep.
+// A step may also carry its time step's point operators (FusedSparse):
+// workgroups appended to the tile grid sample the input, and in plain and
+// save-t steps the workgroup whose tile holds a source node adds the
+// injection (to t as well in save-t) after its sweep.
 // 2-D uses the same scheme with a 64-point x row in LDS and no y axis.
 #pragma once
 
@@ -103,14 +104,20 @@ __device__ __forceinline__ void tile_stores_visible() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 // Injection row j added to the output after the workgroup's sweep: the
-// value the sweep stored (read from L2, past this CU's L1) plus the increment.
-// Only the workgroup whose tile holds the node touches it.
+// value the sweep stored (read from L2, past this CU's L1) plus the increment,
+// and for a save-t step the increment added to t as well.  Only the
+// workgroup whose tile holds the node touches it.
 __device__ __forceinline__ void inj_apply(const InjectOp& a, int j) {
     float s = 0.f;
     for (int e = a.rowptr[j]; e < a.rowptr[j + 1]; ++e) s = __builtin_fmaf(a.w[e], a.values[a.pt[e]], s);
     const int64_t i = a.node[j];
+    const float cs = s * a.scale;
     const float v = __hip_atomic_load(a.field + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    a.field[i] = __builtin_fmaf(a.coef[i], s * a.scale, v);
+    a.field[i] = __builtin_fmaf(a.coef[i], cs, v);
+    if (a.grad) {
+        const float t = __hip_atomic_load(a.grad + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        a.grad[i] = __builtin_fmaf(a.coef[i], cs, t);
+    }
 }
 
 // Workgroups are dealt to the 8 XCDs round-robin by linear id, and each XCD
@@ -360,7 +367,7 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk, FusedSparse fs) {
 
     // Fused injection: the workgroup whose tile holds a node adds its
     // increment once the whole tile is stored.
-    if constexpr (MODE == kStepPlain) {
+    if constexpr (MODE == kStepPlain || MODE == kStepSaveT) {
         const int xb = (int)bx * TX;
         auto in_tile = [&](int j) {
             const int zj = fs.inj_zyx[3 * j], yj = fs.inj_zyx[3 * j + 1], xj = fs.inj_zyx[3 * j + 2];
@@ -479,7 +486,7 @@ step2d(StepArgs a, StencilCoef k, Geo2 g, int zchunk, FusedSparse fs) {
 
     // fused injection (see step3d): the block covers columns [xb, xb + 64)
     // and planes [zb, zb + NW * zchunk)
-    if constexpr (MODE == kStepPlain) {
+    if constexpr (MODE == kStepPlain || MODE == kStepSaveT) {
         const int xb = (int)blockIdx.x * kTileX, zb = (int)blockIdx.y * NW * zchunk;
         auto in_tile = [&](int j) {
             const int zj = fs.inj_zyx[3 * j], xj = fs.inj_zyx[3 * j + 2];
