@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 namespace awe {
 
@@ -112,7 +113,9 @@ hipError_t launch_coef(float* coef, const float* m_phys, const Layout& L, const 
                        const double* eta_z, const double* eta_y, const double* eta_x, double dt, hipStream_t s);
 hipError_t launch_minmax(const float* m, int64_t n, float* partial /* [3 * blocks] */, int blocks, hipStream_t s);
 hipError_t launch_fold(float* grad_phys, const float* g, const Layout& L, const int64_t phys[3], int nbl,
-                       float scale, hipStream_t s);
+                       float scale, const int64_t* wide_cells /* edge and corner cells (fold_wide_cells) */,
+                       int32_t nwide, hipStream_t s);
+std::vector<int64_t> fold_wide_cells(int ndim, const int64_t phys[3], int nbl);
 hipError_t launch_pack(float* dense, const float* pitched, const Layout& L, float scale, hipStream_t s);
 hipError_t launch_pad(float* pitched, const float* m_phys, const Layout& L, const int64_t phys[3], int nbl,
                       hipStream_t s);

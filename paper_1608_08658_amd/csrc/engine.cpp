@@ -166,6 +166,28 @@ uint64_t footprint_binomial_bytes(const awe_geometry* g, int pool_fields) {
     return footprint_bytes(g, 0) + (uint64_t)(pool_fields + 3) * field + (uint64_t)g->nt * g->nsrc * 4;
 }
 
+// Physical cells whose padding preimage is wide along two or more axes (the
+// edges and corners of the absorbing layer), in ascending linear order: the
+// gradient fold gives each of them a workgroup of its own.
+std::vector<int64_t> fold_wide_cells(int ndim, const int64_t phys[3], int nbl) {
+    std::vector<int64_t> out;
+    if (nbl <= 0) return out;
+    const int64_t p0 = phys[0], p1 = phys[1], p2 = phys[2];
+    auto edge = [](int64_t i, int64_t p) { return i == 0 || i == p - 1; };
+    for (int64_t z = 0; z < p0; ++z)
+        for (int64_t y = 0; y < p1; ++y) {
+            const bool ez = edge(z, p0), ey = ndim == 3 && edge(y, p1);
+            const int64_t base = (z * p1 + y) * p2;
+            if (ez && ey) {
+                for (int64_t x = 0; x < p2; ++x) out.push_back(base + x);
+            } else if (ez || ey) {
+                out.push_back(base);
+                out.push_back(base + p2 - 1);
+            }
+        }
+    return out;
+}
+
 // ---------------------------------------------------------------------------
 // damping tables and off-grid point tables
 // ---------------------------------------------------------------------------
@@ -377,6 +399,11 @@ awe_status Plan::init(const awe_geometry* geo) {
         (st = upload(&rec_csr.pt, cr.pt)) || (st = upload(&rec_csr.w, cr.w)))
         return st;
     rec_csr.nrows = (int32_t)cr.node.size();
+    {
+        const std::vector<int64_t> wide = fold_wide_cells(g.ndim, phys, g.nbl);
+        if ((st = upload(&d_fold_cells, wide))) return st;
+        n_fold_cells = (int32_t)wide.size();
+    }
     if ((st = alloc_field(&coef)) || (st = alloc_field(&w0)) || (st = alloc_field(&w1))) return st;
     if ((st = alloc((void**)&d_partial, 3 * 4096 * sizeof(float)))) return st;
     if ((st = alloc((void**)&d_mpart, (kReduceBlocks + 1) * sizeof(double)))) return st;
@@ -890,7 +917,7 @@ awe_status Plan::adjoint(const float* resid, float* src_adj, float* grad_phys, h
             },
             [&](int t, int uc) { return adj_step(t, t >= 1 ? buf(uc) : nullptr); });
         if (st) return st;
-        AWE_HIP(launch_fold(grad_phys, grad, L, phys, g.nbl, (float)(-1.0 / (g.dt * g.dt)), s));
+        AWE_HIP(launch_fold(grad_phys, grad, L, phys, g.nbl, (float)(-1.0 / (g.dt * g.dt)), d_fold_cells, n_fold_cells, s));
         cur = prev = zero;   // the wavefield state no longer holds u[nt-1]
         have_ckpt = false;
         have_grad = true;
@@ -925,7 +952,7 @@ awe_status Plan::adjoint(const float* resid, float* src_adj, float* grad_phys, h
             if ((st = adj_step(n, n >= 1 ? at(n) : nullptr))) return st;
     }
     // g_phys = fold(-(1/dt^2) * accumulated imaging)
-    AWE_HIP(launch_fold(grad_phys, grad, L, phys, g.nbl, (float)(-1.0 / (g.dt * g.dt)), s));
+    AWE_HIP(launch_fold(grad_phys, grad, L, phys, g.nbl, (float)(-1.0 / (g.dt * g.dt)), d_fold_cells, n_fold_cells, s));
     have_grad = true;
     return AWE_OK;
 }

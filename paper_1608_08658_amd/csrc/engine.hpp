@@ -180,6 +180,8 @@ struct awe_plan_s {
     float* rec_w = nullptr;
     awe::DeviceCsr src_csr, rec_csr;
     int32_t* src_zyx = nullptr;     // (z, y, x) of the source nodes when few enough to fuse
+    int64_t* d_fold_cells = nullptr;   // edge and corner cells of the gradient fold
+    int32_t n_fold_cells = 0;
     bool fuse_sparse = true;        // point operators inside the stencil launch (AWE_FUSE=0: off)
     float* d_partial = nullptr;
     double* d_mpart = nullptr;

@@ -107,29 +107,70 @@ minmax_k(const float* m, int64_t n, float* partial) {
 
 // Adjoint of the edge-replication padding, scaled: every physical cell gets
 // scale * (sum of the padded cells that copy it), summed in FP64 in a fixed
-// order.  Interior cells map to one padded cell; edge cells gather the layer.
+// order.  Interior cells map to one padded cell, face cells gather a line of
+// the layer (nbl + 1 cells); edge and corner cells gather a square or a cube
+// of it and are left to fold_wide_k, one workgroup each, so that no thread
+// sums a whole corner block alone.
+struct FoldCell {
+    int64_t z, y, x;                 // physical indices
+    int64_t z_lo, z_hi, y_lo, y_hi, x_lo, x_hi;   // padded preimage
+    int wide;                        // axes whose preimage has more than one cell
+};
+__device__ __forceinline__ FoldCell fold_cell(const PadGeo& p, int64_t i) {
+    FoldCell c;
+    c.x = i % p.p2;
+    c.y = (i / p.p2) % p.p1;
+    c.z = i / (p.p2 * p.p1);
+    c.z_lo = (c.z == 0) ? 0 : c.z + p.nbl;
+    c.z_hi = (c.z == p.p0 - 1) ? p.n0 - 1 : c.z + p.nbl;
+    c.y_lo = c.y_hi = 0;
+    if (p.p1 > 1) {
+        c.y_lo = (c.y == 0) ? 0 : c.y + p.nbl;
+        c.y_hi = (c.y == p.p1 - 1) ? p.n1 - 1 : c.y + p.nbl;
+    }
+    c.x_lo = (c.x == 0) ? 0 : c.x + p.nbl;
+    c.x_hi = (c.x == p.p2 - 1) ? p.n2 - 1 : c.x + p.nbl;
+    c.wide = (c.z_hi > c.z_lo) + (c.y_hi > c.y_lo) + (c.x_hi > c.x_lo);
+    return c;
+}
+
 __global__ void __launch_bounds__(kBlock)
 fold_k(float* grad, const float* g, PadGeo p, float scale) {
     const int64_t total = p.p0 * p.p1 * p.p2;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (int64_t)gridDim.x * kBlock) {
-        const int64_t x = i % p.p2;
-        const int64_t y = (i / p.p2) % p.p1;
-        const int64_t z = i / (p.p2 * p.p1);
-        const int64_t z_lo = (z == 0) ? 0 : z + p.nbl, z_hi = (z == p.p0 - 1) ? p.n0 - 1 : z + p.nbl;
-        int64_t y_lo = 0, y_hi = 0;
-        if (p.p1 > 1) {
-            y_lo = (y == 0) ? 0 : y + p.nbl;
-            y_hi = (y == p.p1 - 1) ? p.n1 - 1 : y + p.nbl;
-        }
-        const int64_t x_lo = (x == 0) ? 0 : x + p.nbl, x_hi = (x == p.p2 - 1) ? p.n2 - 1 : x + p.nbl;
+        const FoldCell c = fold_cell(p, i);
+        if (c.wide >= 2) continue;                  // fold_wide_k
         double s = 0.0;
-        for (int64_t zz = z_lo; zz <= z_hi; ++zz)
-            for (int64_t yy = y_lo; yy <= y_hi; ++yy) {
+        for (int64_t zz = c.z_lo; zz <= c.z_hi; ++zz)
+            for (int64_t yy = c.y_lo; yy <= c.y_hi; ++yy) {
                 const float* row = g + p.origin + zz * p.sz + yy * p.sy;
-                for (int64_t xx = x_lo; xx <= x_hi; ++xx) s += (double)row[xx];
+                for (int64_t xx = c.x_lo; xx <= c.x_hi; ++xx) s += (double)row[xx];
             }
         grad[i] = (float)(s * (double)scale);
     }
+}
+
+// One edge or corner cell per workgroup: each thread sums a fixed strided
+// part of the preimage, then a fixed-order tree adds the parts.
+__global__ void __launch_bounds__(kBlock)
+fold_wide_k(float* grad, const float* g, PadGeo p, float scale, const int64_t* cells) {
+    __shared__ double sh[kBlock];
+    const int64_t i = cells[blockIdx.x];
+    const FoldCell c = fold_cell(p, i);
+    const int64_t ny = c.y_hi - c.y_lo + 1, nx = c.x_hi - c.x_lo + 1;
+    const int64_t count = (c.z_hi - c.z_lo + 1) * ny * nx;
+    double s = 0.0;
+    for (int64_t k = threadIdx.x; k < count; k += kBlock) {
+        const int64_t zz = c.z_lo + k / (ny * nx), rem = k % (ny * nx);
+        s += (double)g[p.origin + zz * p.sz + (c.y_lo + rem / nx) * p.sy + c.x_lo + rem % nx];
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) grad[i] = (float)(sh[0] * (double)scale);
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -241,10 +282,13 @@ hipError_t launch_minmax(const float* m, int64_t n, float* partial, int blocks, 
 }
 
 hipError_t launch_fold(float* grad_phys, const float* g, const Layout& L, const int64_t phys[3], int nbl,
-                       float scale, hipStream_t s) {
+                       float scale, const int64_t* wide_cells, int32_t nwide, hipStream_t s) {
     PadGeo p = pad_geo(L, phys, nbl);
     hipLaunchKernelGGL(fold_k, dim3(blocks_for(p.p0 * p.p1 * p.p2, 8192)), dim3(kBlock), 0, s, grad_phys, g, p,
                        scale);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || nwide <= 0) return e;
+    hipLaunchKernelGGL(fold_wide_k, dim3((unsigned)nwide), dim3(kBlock), 0, s, grad_phys, g, p, scale, wide_cells);
     return hipGetLastError();
 }
 
