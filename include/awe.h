@@ -254,7 +254,13 @@ awe_status awe_misfit(const float* traces_dev, const float* d_obs_dev, int64_t n
  * chunk_steps time steps, two chunks in flight, independently of the others
  * (no batch-wide barrier); a request that finishes is retired and its traces
  * copied to traces_host (host [nt][nrec], kept by the server until the
- * request is done).  Stats' "iterations" counts passes of the engine loop.
+ * request is done).  While requests run the engine waits for no stream but
+ * the one it is working on: plans are set up on their request's stream
+ * without launch timing, and device memory of retired requests stays
+ * allocated (counted against the budget) until nothing runs or the queue
+ * head needs the room, then is freed in one batch.  Stats' "bytes
+ * reserved" counts running requests plus retired ones not yet freed;
+ * "iterations" counts passes of the engine loop.
  * ------------------------------------------------------------------------- */
 enum { AWE_REQ_QUEUED = 0, AWE_REQ_RUNNING = 1, AWE_REQ_DONE = 2, AWE_REQ_FAILED = 3 };
 

@@ -296,7 +296,7 @@ awe_status Plan::alloc_field(float** p) {
     awe_status st = alloc((void**)p, (size_t)L.total * sizeof(float));
     if (st) return st;
     // zero once: the ghost cells must stay zero for the plan's lifetime
-    AWE_HIP(launch_fill(*p, L.total, 0.f, nullptr));
+    AWE_HIP(launch_fill(*p, L.total, 0.f, setup_stream));
     return AWE_OK;
 }
 
@@ -304,7 +304,9 @@ template <class T>
 awe_status Plan::upload(T** dst, const std::vector<T>& v) {
     awe_status st = alloc((void**)dst, v.size() * sizeof(T));
     if (st) return st;
-    if (!v.empty()) AWE_HIP(hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    if (v.empty()) return AWE_OK;
+    AWE_HIP(hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, setup_stream));
+    AWE_HIP(hipStreamSynchronize(setup_stream));   // v may be a temporary
     return AWE_OK;
 }
 
@@ -321,7 +323,13 @@ Plan::~awe_plan_s() {
     for (auto& o : owned) (void)hipFree(o.first);
 }
 
-awe_status Plan::init(const awe_geometry* geo) {
+// All set-up work runs on `setup` and init waits for that stream only, so a
+// plan can be made while other streams keep the device busy.  `timed` =
+// false keeps the autotuner from timing launches (for plans made among
+// running work, where timings would be distorted and the caller stalled).
+awe_status Plan::init(const awe_geometry* geo, hipStream_t setup, bool timed) {
+    setup_stream = setup;
+    timed_tune = timed;
     g = *geo;
     src.assign(geo->src_coords, geo->src_coords + (size_t)geo->nsrc * geo->ndim);
     rec.assign(geo->rec_coords, geo->rec_coords + (size_t)geo->nrec * geo->ndim);
@@ -407,7 +415,8 @@ awe_status Plan::init(const awe_geometry* geo) {
     if ((st = alloc_field(&coef)) || (st = alloc_field(&w0)) || (st = alloc_field(&w1))) return st;
     if ((st = alloc((void**)&d_partial, 3 * 4096 * sizeof(float)))) return st;
     if ((st = alloc((void**)&d_mpart, (kReduceBlocks + 1) * sizeof(double)))) return st;
-    AWE_HIP(hipDeviceSynchronize());
+    AWE_HIP(hipStreamSynchronize(setup_stream));
+    setup_stream = nullptr;
     cur = w0;
     prev = w1;
     return tune(false, nullptr);
@@ -459,8 +468,17 @@ bool nearby_shape(const TuneKey& key, LaunchShape& out) {
 }
 }  // namespace
 
+// The shape used without timing (small grids, AWE_AUTOTUNE=0, plans made
+// among running work).  Measured on 3-D grids of 64^3..464^3, orders
+// 4/8/16: below ~300^3 points, 64x8 tiles with 8-plane chunks are the
+// fastest or within 10% (long chunks leave small grids too few workgroups);
+// above, 28-plane chunks are within 10% alone and the fastest with eight
+// plans running at once, where the extra halo planes of short chunks cost
+// up to 20%.  In 2-D, four-wave blocks of 4-row chunks are within 5% on
+// 128^2..2040^2.
 LaunchShape awe::default_shape(const Layout& L) {
-    return L.ndim == 3 ? LaunchShape{3, 56} : LaunchShape{0, 32};
+    if (L.ndim != 3) return LaunchShape{0, 4};
+    return L.points() < 27000000 ? LaunchShape{1, 8} : LaunchShape{1, 28};
 }
 
 awe_status Plan::tune(bool img, hipStream_t user_stream) {
@@ -489,10 +507,15 @@ awe_status Plan::tune(bool img, hipStream_t user_stream) {
             return AWE_OK;
         }
     }
+    if (!timed_tune) return AWE_OK;   // the built-in shape
     std::vector<LaunchShape> cand;
     if (g.ndim == 3) {
+        // chunks shorter than 28 planes only for the plain step: timed alone
+        // they can win the imaging step too, but in the adjoint sweep (which
+        // alternates with recomputed forward steps) they were ~3% slower
         for (int cfg : {0, 1, 3, 4, 5})
-            for (int zc : {28, 42, 56, 70, 84}) cand.push_back({cfg, zc});
+            for (int zc : {8, 14, 21, 28, 42, 56, 70, 84})
+                if (!img || zc >= 28) cand.push_back({cfg, zc});
     } else {
         for (int zc : {4, 8, 16, 32, 64}) cand.push_back({0, zc});
         for (int zc : {8, 16, 32, 64}) cand.push_back({1, zc});

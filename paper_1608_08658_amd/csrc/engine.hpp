@@ -164,7 +164,7 @@ struct awe_plan_s {
     double vol = 1.0;
     awe::Layout L;
     awe::StencilCoef k{};
-    awe::LaunchShape fwd_shape{3, 56}, img_shape{3, 56};   // stencil launch shapes (forward / imaging)
+    awe::LaunchShape fwd_shape{1, 8}, img_shape{1, 8};   // stencil launch shapes (forward / imaging)
     bool img_tuned = false;
 
     // device buffers owned by the plan
@@ -185,6 +185,8 @@ struct awe_plan_s {
     bool fuse_sparse = true;        // point operators inside the stencil launch (AWE_FUSE=0: off)
     float* d_partial = nullptr;
     double* d_mpart = nullptr;
+    hipStream_t setup_stream = nullptr;   // stream of init's fills and uploads
+    bool timed_tune = true;         // false: take a cached or nearby launch shape, never time candidates
 
     // wavefield state: u[n] and u[n-1]
     const float* cur = nullptr;
@@ -206,7 +208,7 @@ struct awe_plan_s {
     bool have_ckpt = false, have_grad = false;
 
     ~awe_plan_s();
-    awe_status init(const awe_geometry* geo);
+    awe_status init(const awe_geometry* geo, hipStream_t setup = nullptr, bool timed = true);
     awe_status set_model(const float* m, hipStream_t s);
     awe_status forward(const float* wavelet, float* traces, int K, hipStream_t s);
     awe_status forward_binomial(const float* wavelet, float* traces, int snapshots, hipStream_t s);

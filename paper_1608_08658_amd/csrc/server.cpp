@@ -12,6 +12,14 @@
 // budget for the queue.  Each request's arithmetic is exactly that of a plan
 // run alone: the steps are the same kernels on the same data, only
 // interleaved in time with other requests.
+//
+// The engine never waits for the whole device while requests run: a plan is
+// set up on its request's stream (no launch timing: the autotuner takes a
+// cached or nearby shape, else the built-in one), traces are copied out only
+// once the request's last chunk has completed, and streams and events are
+// reused.  hipFree waits for every stream on the device, so a retired
+// request's device memory is kept (counted against the budget) and freed in
+// one batch when nothing runs or when the queue head needs the room.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -55,7 +63,18 @@ struct Request {
     float* d_wav = nullptr;
     float* d_tr = nullptr;
     int next = 0;             // next step index n (u[n+1] is produced next)
-    bool copying = false;     // traces copy-out enqueued
+};
+
+// A stream with its two chunk events, reused by later requests.
+struct Lane {
+    hipStream_t stream = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+};
+
+// Device memory of a retired request, awaiting a batched free.
+struct Grave {
+    awe_plan plan = nullptr;
+    float* bufs[3] = {nullptr, nullptr, nullptr};
 };
 
 }  // namespace
@@ -75,31 +94,71 @@ struct awe_server_s {
     std::deque<Request*> queue;
     std::vector<Request*> active;
     std::map<int64_t, std::unique_ptr<Request>> all;
+    std::vector<Lane> lanes;     // idle streams
+    std::vector<Grave> graves;   // retired requests' device memory
+    uint64_t grave_bytes = 0;
     bool stop = false;
     std::thread engine;
 
     void run();
     bool start(Request* r, std::string& err);
     void finish(Request* r, int state, const std::string& err);
+    void free_graves();
+    void release_lanes();
 };
 
-void awe_server_s::finish(Request* r, int state, const std::string& err) {
-    // caller does not hold mu
-    if (r->plan) awe_plan_destroy(r->plan);
-    r->plan = nullptr;
-    if (r->stream) (void)hipStreamSynchronize(r->stream);
-    for (hipEvent_t& e : r->ev) {
-        if (e) (void)hipEventDestroy(e);
-        e = nullptr;
+void awe_server_s::free_graves() {
+    // engine thread (or after it has ended); the first hipFree waits for the device
+    std::vector<Grave> g;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        g.swap(graves);
     }
-    if (r->stream) (void)hipStreamDestroy(r->stream);
-    for (float* p : {r->d_m, r->d_wav, r->d_tr})
-        if (p) (void)hipFree(p);
+    for (Grave& x : g) {
+        if (x.plan) awe_plan_destroy(x.plan);
+        for (float* p : x.bufs)
+            if (p) (void)hipFree(p);
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    if (graves.empty()) grave_bytes = 0;
+}
+
+void awe_server_s::release_lanes() {
+    for (Lane& l : lanes) {
+        for (hipEvent_t e : l.ev)
+            if (e) (void)hipEventDestroy(e);
+        if (l.stream) (void)hipStreamDestroy(l.stream);
+    }
+    lanes.clear();
+}
+
+void awe_server_s::finish(Request* r, int state, const std::string& err) {
+    // caller does not hold mu; waits for r's own stream only
+    if (r->stream) (void)hipStreamSynchronize(r->stream);
+    Grave gr;
+    gr.plan = r->plan;
+    gr.bufs[0] = r->d_m;
+    gr.bufs[1] = r->d_wav;
+    gr.bufs[2] = r->d_tr;
+    Lane ln;
+    ln.stream = r->stream;
+    ln.ev[0] = r->ev[0];
+    ln.ev[1] = r->ev[1];
+    r->plan = nullptr;
     r->d_m = r->d_wav = r->d_tr = nullptr;
     r->stream = nullptr;
+    r->ev[0] = r->ev[1] = nullptr;
     std::vector<float>().swap(r->m);
     std::vector<float>().swap(r->wavelet);
     std::lock_guard<std::mutex> lk(mu);
+    if (gr.plan || gr.bufs[0] || gr.bufs[1] || gr.bufs[2]) {
+        graves.push_back(gr);
+        grave_bytes += r->bytes;
+    }
+    if (ln.stream) lanes.push_back(ln);
+    else
+        for (hipEvent_t e : ln.ev)
+            if (e) (void)hipEventDestroy(e);
     r->state = state;
     r->err = err;
     r->t[3] = now_s(t0);
@@ -115,11 +174,30 @@ bool awe_server_s::start(Request* r, std::string& err) {
         err = std::string(what) + ": " + hipGetErrorString(e);
         return false;
     };
-    awe_status st = awe_plan_create(&r->g, &r->plan);
-    if (st) { err = awe_last_error(); return false; }
-    if (!hip_ok(hipStreamCreateWithFlags(&r->stream, hipStreamNonBlocking), "hipStreamCreate")) return false;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        if (!lanes.empty()) {
+            r->stream = lanes.back().stream;
+            r->ev[0] = lanes.back().ev[0];
+            r->ev[1] = lanes.back().ev[1];
+            lanes.pop_back();
+        }
+    }
+    r->ev_head = r->inflight = 0;
+    if (!r->stream && !hip_ok(hipStreamCreateWithFlags(&r->stream, hipStreamNonBlocking), "hipStreamCreate"))
+        return false;
     for (hipEvent_t& e : r->ev)
-        if (!hip_ok(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate")) return false;
+        if (!e && !hip_ok(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate")) return false;
+    awe_status st = AWE_OK;
+    try {
+        r->plan = new awe_plan_s();
+        st = r->plan->init(&r->g, r->stream, false);
+    } catch (const std::bad_alloc&) {
+        st = fail(AWE_ENOMEM, "host allocation failed");
+    } catch (...) {
+        st = fail(AWE_EINVAL, "unexpected exception in the library");
+    }
+    if (st) { err = awe_last_error(); return false; }
     const size_t nm = r->m.size(), nw = r->wavelet.size(), ntr = (size_t)r->g.nt * r->g.nrec;
     if (!hip_ok(hipMalloc(&r->d_m, nm * sizeof(float)), "hipMalloc")) return false;
     if (nw && !hip_ok(hipMalloc(&r->d_wav, nw * sizeof(float)), "hipMalloc")) return false;
@@ -145,13 +223,22 @@ void awe_server_s::run() {
     (void)hipSetDevice(device);
     for (;;) {
         std::vector<Request*> admitted;
+        bool flush = false;
         {
             std::unique_lock<std::mutex> lk(mu);
-            wake.wait(lk, [&] { return stop || !queue.empty() || !active.empty(); });
-            if (stop && active.empty()) break;
+            if (active.empty() && !graves.empty()) {
+                flush = true;   // nothing runs: freeing stalls no one
+            } else {
+                wake.wait(lk, [&] { return stop || !queue.empty() || !active.empty(); });
+                if (stop && active.empty()) break;
+            }
             // FIFO admission: the head waits until it fits (no overtaking).
-            while (!stop && !queue.empty() && (int)active.size() + (int)admitted.size() < max_active &&
+            while (!flush && !stop && !queue.empty() && (int)active.size() + (int)admitted.size() < max_active &&
                    reserved + queue.front()->bytes <= budget) {
+                if (reserved + grave_bytes + queue.front()->bytes > budget) {
+                    flush = admitted.empty();   // the head fits once retired memory is freed
+                    break;
+                }
                 Request* r = queue.front();
                 queue.pop_front();
                 reserved += r->bytes;
@@ -160,6 +247,10 @@ void awe_server_s::run() {
                 ++n_admitted;
                 admitted.push_back(r);
             }
+        }
+        if (flush) {
+            free_graves();
+            continue;
         }
         for (Request* r : admitted) {
             std::string err;
@@ -194,23 +285,15 @@ void awe_server_s::run() {
                 --r->inflight;
                 progressed = true;
             }
-            while (!failed && !r->copying && r->inflight < 2) {
-                const int last = r->g.nt - 1;
+            const int last = r->g.nt - 1;
+            while (!failed && r->inflight < 2 && r->next < last) {
                 const int n = std::min(chunk, last - r->next);
-                if (n > 0) {
-                    if (r->plan->step(r->next, n, r->d_wav, r->d_tr, r->stream)) {
-                        err = awe_last_error();
-                        failed = true;
-                        break;
-                    }
-                    r->next += n;
+                if (r->plan->step(r->next, n, r->d_wav, r->d_tr, r->stream)) {
+                    err = awe_last_error();
+                    failed = true;
+                    break;
                 }
-                if (r->next >= last) {
-                    const size_t ntr = (size_t)r->g.nt * r->g.nrec;
-                    if (ntr) (void)hipMemcpyAsync(r->traces_host, r->d_tr, ntr * sizeof(float), hipMemcpyDeviceToHost,
-                                                  r->stream);
-                    r->copying = true;
-                }
+                r->next += n;
                 const hipError_t e = hipEventRecord(r->ev[r->ev_head], r->stream);
                 if (e != hipSuccess) {
                     err = hipGetErrorString(e);
@@ -221,7 +304,21 @@ void awe_server_s::run() {
                 ++r->inflight;
                 progressed = true;
             }
-            if (failed || (r->copying && r->inflight == 0)) {
+            bool done = false;
+            if (!failed && r->next >= last && r->inflight == 0) {
+                // every step has completed, so the copy-out waits for nothing else
+                const size_t ntr = (size_t)r->g.nt * r->g.nrec;
+                hipError_t e = hipSuccess;
+                if (ntr) e = hipMemcpyAsync(r->traces_host, r->d_tr, ntr * sizeof(float), hipMemcpyDeviceToHost,
+                                            r->stream);
+                if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
+                if (e != hipSuccess) {
+                    err = hipGetErrorString(e);
+                    failed = true;
+                }
+                done = true;
+            }
+            if (failed || done) {
                 { std::lock_guard<std::mutex> lk(mu); active.erase(std::find(active.begin(), active.end(), r)); }
                 finish(r, failed ? AWE_REQ_FAILED : AWE_REQ_DONE, err);
                 progressed = true;
@@ -332,7 +429,7 @@ awe_status awe_server_stats(awe_server srv, int64_t* out) {
     out[3] = srv->n_failed;
     out[4] = (int64_t)srv->active.size();
     out[5] = (int64_t)srv->queue.size();
-    out[6] = (int64_t)srv->reserved;
+    out[6] = (int64_t)(srv->reserved + srv->grave_bytes);
     out[7] = srv->iterations;
     return AWE_OK;
 }
@@ -352,6 +449,8 @@ awe_status awe_server_destroy(awe_server srv) {
         srv->changed.notify_all();
     }
     if (srv->engine.joinable()) srv->engine.join();
+    srv->free_graves();
+    srv->release_lanes();
     delete srv;
     return AWE_OK;
 }

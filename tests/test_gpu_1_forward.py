@@ -172,7 +172,7 @@ def test_every_launch_shape_is_bitwise_identical(monkeypatch):
     shot = small_3d_shot(310, 8, nt=40)
     dt = shot_dt(shot)
     ref = None
-    for cfg in ("0,7", "1,16", "2,33", "3,100", "3,56", "4,9", "5,30"):
+    for cfg in ("0,7", "1,8", "1,16", "2,33", "3,100", "3,56", "4,9", "5,30"):
         out = _forward_with_env(monkeypatch, shot, dt, {"AWE_TILE": cfg})
         if ref is None:
             ref = out

@@ -53,6 +53,12 @@ def test_results_in_the_mix_equal_results_alone():
         alone = _alone(shot, dt, w)
         log(f"  {shot.name}: bitwise equal {np.array_equal(tr.astype(np.float64), alone)}")
         assert np.array_equal(tr.astype(np.float64), alone), shot.name
+    # with nothing running, the retired requests' memory is freed
+    import time
+    t0 = time.time()
+    while srv.stats()["bytes_reserved"] and time.time() - t0 < 30:
+        time.sleep(0.01)
+    assert srv.stats()["bytes_reserved"] == 0
     srv.close()
 
 
