@@ -321,6 +321,38 @@ def bench_born(torch, awe, synth, n=256, nt=1000):
             "algorithmic_GBps": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS, "finite": finite}
 
 
+def bench_small_2d(torch, awe, synth, reps=5):
+    """The small 2-D shot (101 x 101 + 10-point layer = 121 x 121 computed,
+    order 4, 500 samples): 57 KiB per field, so each step is bound by launch
+    latency, not HBM; reported as time per step, not against the roofline."""
+    shot = synth.config_2d_small()
+    dt = shot.dt_factor * awe.dt_max(2, shot.order, shot.spacing, 1500.0)
+    plan = awe.Plan(shape=shot.shape, spacing=shot.spacing, space_order=shot.order, nbl=shot.nbl, dt=dt, nt=shot.nt,
+                    src_coords=shot.src_coords, rec_coords=shot.rec_coords, damp_power=shot.damp_power,
+                    damp_R=shot.damp_R, damp_vref=shot.damp_vref)
+    plan.set_model(torch.tensor(shot.m, dtype=torch.float32, device="cuda"))
+    w = torch.tensor(shot.wavelet(dt), dtype=torch.float32, device="cuda")
+    plan.forward(w)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    times = []
+    for _ in range(reps):
+        ev[0].record()
+        tr = plan.forward(w)
+        ev[1].record()
+        torch.cuda.synchronize()
+        times.append(ev[0].elapsed_time(ev[1]) / 1e3)
+    t = float(np.median(times))
+    npad = int(np.prod(plan.padded))
+    finite = bool(torch.isfinite(tr).all().item())
+    shape = plan.info()["forward_shape"]
+    plan.close()
+    log(f"small 2-D: {shot.nt} samples in {t * 1e3:.2f} ms, {t / (shot.nt - 1) * 1e6:.2f} us per step")
+    return {"workload": "2-D 101x101 + 10-point layer (121x121 computed), h = 10 m, v = 1500 m/s, order 4, "
+                        "500 samples, 10 Hz Ricker at the centre, 101 receivers",
+            "nt": shot.nt, "forward_s": t, "us_per_step": t / (shot.nt - 1) * 1e6,
+            "grid_pt_updates_per_s": npad * (shot.nt - 1) / t, "launch_shape": list(shape), "finite": finite}
+
+
 def bench_paper_example(torch, awe, synth):
     """The paper's 3-D run (Sec. V.D): 281 x 281 x 150 computed points,
     h = 15 m, order 14, 10 Hz Ricker, 1 s modelled, synthetic layered model."""
@@ -364,6 +396,7 @@ def main():
                     help="stored states of the binomial-checkpointing gradient (-1 = skip it)")
     ap.add_argument("--paper-example", type=int, default=1, help="run the paper's 3-D example workload (0 = skip)")
     ap.add_argument("--born", type=int, default=1, help="time Born modelling on the forward grid (0 = skip)")
+    ap.add_argument("--small-2d", type=int, default=1, help="time the small 2-D shot (0 = skip)")
     ap.add_argument("--serve-requests", type=int, default=64, help="requests in the serving run (0 = skip)")
     ap.add_argument("--serve-scale", type=float, default=0.5, help="size/step scale of the serving mix")
     ap.add_argument("--served-gradient-shots", type=int, default=0,
@@ -461,6 +494,11 @@ def main():
         log("paper example workload ...")
         paper = bench_paper_example(torch, awe, synth)
 
+    small = None
+    if args.small_2d:
+        log("small 2-D workload ...")
+        small = bench_small_2d(torch, awe, synth)
+
     born = None
     if args.born:
         log("Born modelling ...")
@@ -516,6 +554,7 @@ def main():
         "cpu_baseline": base,
         "gradient": grad,
         "paper_example": paper,
+        "small_2d": small,
         "born": born,
         "serving": serve,
         "served_gradients": shots,

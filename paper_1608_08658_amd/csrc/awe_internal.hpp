@@ -109,6 +109,38 @@ struct FusedSparse {
     const int32_t* inj_zyx = nullptr;  // [nrows][3]: (z, y, x) grid indices of the nodes (y = 0 in 2-D)
     SampleOp smp;                      // smp.field is the step's input
 };
+// 2-D forward steps in blocks of up to tb_steps(M) per launch
+// (kernels_stencil2d_tb.hip): the point operators of every step travel with
+// the launch.  Injection takes the source CSR rows (at most kFuseMaxNodes
+// nodes) and wavelet rows n0..; sampling takes each receiver's base node and
+// weights and a list of receivers by tb_tile() x tb_tile() tile of that node.
+struct TbPoints {
+    const float* wavelet = nullptr;      // [nt][nsrc]; NULL: no injection
+    int32_t nsrc = 0;
+    int32_t nrows = 0;                   // source CSR rows (grid nodes)
+    const int64_t* src_node = nullptr;
+    const int32_t* src_rowptr = nullptr;
+    const int32_t* src_pt = nullptr;
+    const float* src_w = nullptr;
+    const int32_t* src_zyx = nullptr;    // [nrows][3]
+    float src_scale = 1.f;
+    float* traces = nullptr;             // [nt][nrec]; NULL: no sampling
+    int32_t nrec = 0;
+    int32_t first_row = 0;               // steps s < first_row of the launch record nothing
+    const int32_t* rec_zx = nullptr;     // [nrec][2]: (z, x) of the receiver's lowest node
+    const float* rec_w = nullptr;        // [nrec][4]: weights in corner order
+    const int32_t* tile_ptr = nullptr;   // [tiles + 1]
+    const int32_t* tile_rec = nullptr;   // [nrec]: receivers by tile, ascending
+    float rec_scale = 1.f;
+};
+int tb_steps(int half);
+int tb_tile();
+int tb_max_tile_receivers();
+// (uc, up) = (u[n0], u[n0-1]) -> (out_c, out_p) = (u[n0+nsteps], u[n0+nsteps-1]);
+// the outputs must be distinct from the inputs (tiles read halos of others).
+hipError_t launch_step2d_tb(const Layout& L, const StencilCoef& k, const float* uc, const float* up, float* out_c,
+                            float* out_p, const float* coef, const float* eta_z, const float* eta_x,
+                            const TbPoints& p, int n0, int nsteps, hipStream_t s);
 hipError_t launch_coef(float* coef, const float* m_phys, const Layout& L, const int64_t phys[3], int nbl,
                        const double* eta_z, const double* eta_y, const double* eta_x, double dt, hipStream_t s);
 hipError_t launch_minmax(const float* m, int64_t n, float* partial /* [3 * blocks] */, int blocks, hipStream_t s);

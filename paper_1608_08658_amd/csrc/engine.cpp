@@ -151,6 +151,8 @@ uint64_t footprint_bytes(const awe_geometry* g, int K) {
     b += (uint64_t)(pad[0] + pad[1] + pad[2]) * 12;                            // eta tables (fp32 + fp64)
     b += (uint64_t)(g->nsrc + g->nrec) * corners * (8 + 4) * 2 + 8 * corners * (g->nsrc + g->nrec + 2);
     b += 64 * 1024;                                                            // reduction scratch
+    if (g->ndim == 2)                                                          // blocked steps: two more fields
+        b += 2 * field + (uint64_t)g->nrec * 12 + (uint64_t)(pad[0] / 64 + 2) * (pad[2] / 64 + 2) * 4;
     if (K > 0) {
         b += (uint64_t)(stored_times(g->nt, K).size() + segment_slots(g->nt, K) + 3) * field;  // + mu x2, g
         b += (uint64_t)g->nt * g->nsrc * 4;                                    // wavelet copy
@@ -412,6 +414,36 @@ awe_status Plan::init(const awe_geometry* geo, hipStream_t setup, bool timed) {
         if ((st = upload(&d_fold_cells, wide))) return st;
         n_fold_cells = (int32_t)wide.size();
     }
+    // blocked 2-D steps (orders 2 and 4, grids up to 3M points: where they
+    // beat one step per launch): receivers by tile of their lowest node, and
+    // two more fields
+    constexpr int64_t kTbMaxPoints = 3000000;
+    const char* tb_env = std::getenv("AWE_TB");
+    if (g.ndim == 2 && tb_steps(half) > 1 && L.points() <= kTbMaxPoints && fuse_sparse &&
+        !(tb_env && tb_env[0] == '0') && src_csr.nrows <= kFuseMaxNodes &&
+        (src_csr.nrows == 0 || src_zyx)) {
+        const int64_t tile = tb_tile(), gxn = (L.n[2] + tile - 1) / tile, gzn = (L.n[0] + tile - 1) / tile;
+        std::vector<int32_t> zx(2 * (size_t)g.nrec), ptr(gxn * gzn + 1, 0), list(g.nrec), tile_of(g.nrec);
+        for (int r = 0; r < g.nrec; ++r) {
+            const int64_t rel = tr.node[(size_t)r * corners] - L.origin;   // corner 0: the lowest node
+            const int64_t z = rel / L.sz, x = rel % L.sz;
+            zx[2 * (size_t)r] = (int32_t)z;
+            zx[2 * (size_t)r + 1] = (int32_t)x;
+            tile_of[r] = (int32_t)((z / tile) * gxn + x / tile);
+            ++ptr[tile_of[r] + 1];
+        }
+        int most = 0;
+        for (size_t t = 1; t < ptr.size(); ++t) most = std::max(most, ptr[t]);
+        for (size_t t = 1; t < ptr.size(); ++t) ptr[t] += ptr[t - 1];
+        if (most <= tb_max_tile_receivers()) {   // else one step per launch
+            std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+            for (int r = 0; r < g.nrec; ++r) list[fill[tile_of[r]]++] = r;
+            if ((st = upload(&d_rec_zx, zx)) || (st = upload(&d_tile_ptr, ptr)) || (st = upload(&d_tile_rec, list)) ||
+                (st = alloc_field(&w2)) || (st = alloc_field(&w3)))
+                return st;
+            tb_T = tb_steps(half);
+        }
+    }
     if ((st = alloc_field(&coef)) || (st = alloc_field(&w0)) || (st = alloc_field(&w1))) return st;
     if ((st = alloc((void**)&d_partial, 3 * 4096 * sizeof(float)))) return st;
     if ((st = alloc((void**)&d_mpart, (kReduceBlocks + 1) * sizeof(double)))) return st;
@@ -644,6 +676,42 @@ awe_status Plan::advance(const float* uc, const float* up, float* out, const flo
     return AWE_OK;
 }
 
+// Steps n0 .. n0+nsteps-1 (nsteps <= tb_T) of a 2-D plain forward in one
+// launch, with the source injected at each step and trace rows n0+s for s >=
+// first_row recorded from u[n0+s].  The results go to two work buffers other
+// than the current pair.
+awe_status Plan::advance_tb(int n0, int nsteps, const float* wavelet, float* traces, int first_row, hipStream_t s) {
+    float* outs[2] = {nullptr, nullptr};
+    int n = 0;
+    for (float* b : {w0, w1, w2, w3})
+        if (b != cur && b != prev && n < 2) outs[n++] = b;
+    TbPoints p;
+    if (wavelet && g.nsrc > 0 && src_csr.nrows > 0) {
+        p.wavelet = wavelet;
+        p.nsrc = g.nsrc;
+        p.nrows = src_csr.nrows;
+        p.src_node = src_csr.node;
+        p.src_rowptr = src_csr.rowptr;
+        p.src_pt = src_csr.pt;
+        p.src_w = src_csr.w;
+        p.src_zyx = src_zyx;
+        p.src_scale = (float)(1.0 / vol);
+    }
+    if (traces && g.nrec > 0) {
+        p.traces = traces;
+        p.nrec = g.nrec;
+        p.first_row = first_row;
+        p.rec_zx = d_rec_zx;
+        p.rec_w = rec_w;
+        p.tile_ptr = d_tile_ptr;
+        p.tile_rec = d_tile_rec;
+    }
+    AWE_HIP(launch_step2d_tb(L, k, cur, prev, outs[0], outs[1], coef, d_ez, d_ex, p, n0, nsteps, s));
+    cur = outs[0];
+    prev = outs[1];
+    return AWE_OK;
+}
+
 void Plan::release_periodic() {
     for (auto& kv : stored) release(kv.second);
     stored.clear();
@@ -729,7 +797,14 @@ awe_status Plan::forward(const float* wavelet, float* traces, int K, hipStream_t
     // Trace row n is recorded in the launch that injects into u[n+1]; row 0
     // samples u[0] = 0 and the last row follows the loop.
     float* const tr = (traces && g.nrec > 0) ? traces : nullptr;
-    for (int n = 0; n + 1 < g.nt; ++n) {
+    if (K == 0 && tb_T > 0) {
+        for (int n = 0; n + 1 < g.nt;) {
+            const int m = std::min(tb_T, g.nt - 1 - n);
+            if ((st = advance_tb(n, m, g.nsrc ? wavelet : nullptr, tr, 0, s))) return st;
+            n += m;
+        }
+    }
+    for (int n = 0; n + 1 < g.nt && !(K == 0 && tb_T > 0); ++n) {
         float* dst = nullptr;
         if (K > 0) {
             auto it = stored.find(n + 1);
@@ -783,7 +858,8 @@ awe_status Plan::forward_binomial(const float* wavelet, float* traces, int snaps
 }
 
 float* Plan::pick_work_dst() {
-    if (prev == w0 || prev == w1) return const_cast<float*>(prev);   // in place over u[n-1]
+    if (prev == w0 || prev == w1 || (prev && (prev == w2 || prev == w3)))
+        return const_cast<float*>(prev);   // in place over u[n-1]
     return cur == w0 ? w1 : w0;
 }
 
@@ -795,7 +871,14 @@ awe_status Plan::step(int n0, int nsteps, const float* wavelet, float* traces, h
     // Row n+1 receives the sample of u[n+1]: recorded by the next step's
     // injection launch, the last one after the loop.  Row n0 is not written.
     float* const tr = (traces && g.nrec > 0) ? traces : nullptr;
-    for (int n = n0; n < n0 + nsteps; ++n) {
+    if (tb_T > 0) {
+        for (int n = n0; n < n0 + nsteps;) {
+            const int m = std::min(tb_T, n0 + nsteps - n);
+            if ((st = advance_tb(n, m, (wavelet && g.nsrc) ? wavelet : nullptr, tr, n == n0 ? 1 : 0, s))) return st;
+            n += m;
+        }
+    }
+    for (int n = n0; n < n0 + nsteps && tb_T == 0; ++n) {
         float* dst = pick_work_dst();
         if ((st = advance(cur, prev, dst, (wavelet && g.nsrc) ? wavelet + (size_t)n * g.nsrc : nullptr,
                           (tr && n > n0) ? tr + (size_t)n * g.nrec : nullptr, s)))

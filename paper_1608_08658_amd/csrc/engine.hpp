@@ -183,6 +183,9 @@ struct awe_plan_s {
     int64_t* d_fold_cells = nullptr;   // edge and corner cells of the gradient fold
     int32_t n_fold_cells = 0;
     bool fuse_sparse = true;        // point operators inside the stencil launch (AWE_FUSE=0: off)
+    int tb_T = 0;                   // 2-D plain steps per launch (0: one step per launch; AWE_TB=0)
+    float *w2 = nullptr, *w3 = nullptr;   // outputs of blocked 2-D launches
+    int32_t *d_rec_zx = nullptr, *d_tile_ptr = nullptr, *d_tile_rec = nullptr;
     float* d_partial = nullptr;
     double* d_mpart = nullptr;
     hipStream_t setup_stream = nullptr;   // stream of init's fills and uploads
@@ -223,6 +226,7 @@ struct awe_plan_s {
     void release(void* p);
     awe_status advance(const float* uc, const float* up, float* out, const float* q_row, float* rec_row,
                        hipStream_t s);
+    awe_status advance_tb(int n0, int nsteps, const float* wavelet, float* traces, int first_row, hipStream_t s);
     awe::InjectOp src_op(float* field, const float* q_row, float* t_acc) const;
     awe::SampleOp rec_op(float* row, const float* field) const;
     awe_status ensure_gradient_storage(int K);
