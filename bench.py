@@ -344,13 +344,12 @@ def bench_small_2d(torch, awe, synth, reps=5):
     t = float(np.median(times))
     npad = int(np.prod(plan.padded))
     finite = bool(torch.isfinite(tr).all().item())
-    shape = plan.info()["forward_shape"]
     plan.close()
     log(f"small 2-D: {shot.nt} samples in {t * 1e3:.2f} ms, {t / (shot.nt - 1) * 1e6:.2f} us per step")
     return {"workload": "2-D 101x101 + 10-point layer (121x121 computed), h = 10 m, v = 1500 m/s, order 4, "
                         "500 samples, 10 Hz Ricker at the centre, 101 receivers",
             "nt": shot.nt, "forward_s": t, "us_per_step": t / (shot.nt - 1) * 1e6,
-            "grid_pt_updates_per_s": npad * (shot.nt - 1) / t, "launch_shape": list(shape), "finite": finite}
+            "grid_pt_updates_per_s": npad * (shot.nt - 1) / t, "finite": finite}
 
 
 def bench_paper_example(torch, awe, synth):
