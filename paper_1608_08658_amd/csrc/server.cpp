@@ -35,6 +35,7 @@
 
 #include "awe.h"
 #include "engine.hpp"
+#include "server_policy.hpp"
 
 using awe::fail;
 
@@ -226,19 +227,21 @@ void awe_server_s::run() {
         bool flush = false;
         {
             std::unique_lock<std::mutex> lk(mu);
-            if (active.empty() && !graves.empty()) {
-                flush = true;   // nothing runs: freeing stalls no one
-            } else {
+            if (!active.empty() || graves.empty()) {   // else free the retired memory first
                 wake.wait(lk, [&] { return stop || !queue.empty() || !active.empty(); });
-                if (stop && active.empty()) break;
+                if (stop && active.empty() && graves.empty()) break;
             }
-            // FIFO admission: the head waits until it fits (no overtaking).
-            while (!flush && !stop && !queue.empty() && (int)active.size() + (int)admitted.size() < max_active &&
-                   reserved + queue.front()->bytes <= budget) {
-                if (reserved + grave_bytes + queue.front()->bytes > budget) {
-                    flush = admitted.empty();   // the head fits once retired memory is freed
-                    break;
-                }
+            // FIFO admission (server_policy.hpp)
+            awe::AdmitState as;
+            as.budget = budget;
+            as.reserved = reserved;
+            as.retired = grave_bytes;
+            as.running = (int)active.size();
+            as.max_active = max_active;
+            const awe::AdmitResult ar =
+                awe::admit_fifo(as, stop ? 0 : (int)queue.size(), [&](int i) { return queue[i]->bytes; });
+            flush = ar.free_retired;
+            for (int i = 0; i < ar.count; ++i) {
                 Request* r = queue.front();
                 queue.pop_front();
                 reserved += r->bytes;
