@@ -579,13 +579,22 @@ awe_status Plan::tune(bool img, hipStream_t user_stream) {
             if (e == hipSuccess) best_of[i] = std::min(best_of[i], ms);
         }
     }
+    // Candidates within 1% of the fastest are a tie at this timing's noise;
+    // of those, the longest z-chunk (fewest warm-up planes re-read), then
+    // the faster.  Without this, near-equal shapes flip from plan to plan.
+    float fastest = 1e30f;
+    for (size_t i = 0; i < cand.size(); ++i) fastest = std::min(fastest, best_of[i]);
     LaunchShape best = shape;
     float best_ms = 1e30f;
-    for (size_t i = 0; i < cand.size(); ++i)
-        if (best_of[i] < best_ms) {
-            best_ms = best_of[i];
+    int best_zc = -1;
+    for (size_t i = 0; i < cand.size(); ++i) {
+        if (!(best_of[i] <= 1.01f * fastest)) continue;
+        if (cand[i].zchunk > best_zc || (cand[i].zchunk == best_zc && best_of[i] < best_ms)) {
             best = cand[i];
+            best_zc = cand[i].zchunk;
+            best_ms = best_of[i];
         }
+    }
     if (e != hipSuccess) st = fail(AWE_EHIP, "autotune: %s", hipGetErrorString(e));
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
