@@ -184,7 +184,7 @@ def bench_gradient(torch, awe, synth, n=400, nt=2000, snapshots=20):
     }
 
 
-def bench_serve(awe, synth, count=64, scale=0.5, seed=4, max_active=16, chunk=64):
+def bench_serve(awe, synth, count=200, scale=0.5, seed=4, max_active=16, chunk=64):
     """Continuous-batching shot server under Poisson load.  First the
     saturation rate mu (every request submitted at once), then Poisson
     arrivals at 0.5, 0.8 and 0.95 mu with p50/p99 latency (result on the
@@ -396,7 +396,7 @@ def main():
     ap.add_argument("--paper-example", type=int, default=1, help="run the paper's 3-D example workload (0 = skip)")
     ap.add_argument("--born", type=int, default=1, help="time Born modelling on the forward grid (0 = skip)")
     ap.add_argument("--small-2d", type=int, default=1, help="time the small 2-D shot (0 = skip)")
-    ap.add_argument("--serve-requests", type=int, default=64, help="requests in the serving run (0 = skip)")
+    ap.add_argument("--serve-requests", type=int, default=200, help="requests per serving point (0 = skip)")
     ap.add_argument("--serve-scale", type=float, default=0.5, help="size/step scale of the serving mix")
     ap.add_argument("--served-gradient-shots", type=int, default=0,
                     help="shots of the 300^3 served-gradient workload (0 = skip; 32 is the full workload)")
