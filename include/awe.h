@@ -139,7 +139,14 @@ awe_status awe_footprint_binomial(const awe_geometry* g, int32_t snapshots, uint
  * Validate `g`, build the off-grid point tables and allocate the plan's
  * forward fields on the current HIP device.  Coordinates outside the padded
  * grid are AWE_EINVAL.  The plan owns every device buffer it allocates;
- * awe_plan_destroy frees them.  Synchronous.
+ * awe_plan_destroy frees them.  Synchronous (waits for the null stream, on
+ * which its set-up runs).  For 3-D grids of 4M points and more and 2-D grids
+ * of 64K points and more, the first plan of a grid size times the stencil's
+ * launch shapes on its own buffers (the paper's block-size autotuning,
+ * Sec. IV.B.3; tens to hundreds of launches) unless a shape for the same
+ * order and a size within 30% in points is already known in the process;
+ * the environment variables AWE_TILE=cfg,zchunk and AWE_AUTOTUNE=0 pin or
+ * skip it.  Every shape gives bit-identical results.
  */
 awe_status awe_plan_create(const awe_geometry* g, awe_plan* out);
 awe_status awe_plan_destroy(awe_plan plan);
