@@ -144,7 +144,8 @@ awe_status awe_footprint_binomial(const awe_geometry* g, int32_t snapshots, uint
  * of 64K points and more, the first plan of a grid size times the stencil's
  * launch shapes on its own buffers (the paper's block-size autotuning,
  * Sec. IV.B.3; tens to hundreds of launches) unless a shape for the same
- * order and a size within 30% in points is already known in the process;
+ * order and size (3-D: a size within 30% in points) is already known in the
+ * process;
  * the environment variables AWE_TILE=cfg,zchunk and AWE_AUTOTUNE=0 pin or
  * skip it.  Every shape gives bit-identical results.
  */
