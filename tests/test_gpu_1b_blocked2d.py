@@ -102,3 +102,11 @@ def test_blocked_2d_large_grid_and_paper_small_case(monkeypatch):
     small = synth.config_2d_small()
     dt = shot_dt(small)
     _check(_run(monkeypatch, small, dt, blocked=True), _run(monkeypatch, small, dt, blocked=False), small, "small")
+
+
+@pytest.mark.parametrize("nt", [1, 2, 3, 5])
+def test_blocked_2d_tiny_step_counts(monkeypatch, nt):
+    # no step, one step (a launch of one), and partial blocks
+    shot = _seam_shot(2, nt=nt, seed=800 + nt)
+    dt = shot_dt(shot)
+    _check(_run(monkeypatch, shot, dt, blocked=True), _run(monkeypatch, shot, dt, blocked=False), shot, nt)
