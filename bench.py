@@ -404,8 +404,8 @@ def main():
                     help="also run a plain device-to-device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (shots would shard one per GPU, "
-              "see DESIGN.md); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (independent shots would shard "
+              "one per GPU, one process each); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
