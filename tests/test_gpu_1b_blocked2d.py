@@ -33,6 +33,7 @@ def _seam_shot(order, nt, seed):
 
 
 def _run(monkeypatch, shot, dt, blocked, chunks=None):
+    monkeypatch.delenv("AWE_FUSE", raising=False)   # blocking needs the point operators in the launch
     if blocked:
         monkeypatch.delenv("AWE_TB", raising=False)
     else:
