@@ -24,14 +24,16 @@ constexpr int kTbTile = 32;
 constexpr int kTbRecPerThread = 2;   // receivers per tile: at most 512
 constexpr int kTbGroup = 4;          // rows per thread evaluated together
 
-// Steps per launch, a halo H = T*M of 8 points.  Measured against one step
-// per launch (the tuned one-step kernel, 201 steps, a source and 200
-// receivers): order 2 is 2.4x faster on 121^2..400^2 grids and 1.7-1.8x on
-// 1040^2..1500^2; order 4 1.5-1.7x on 121^2..640^2 and 1.1-1.25x on
-// 1040^2..1500^2 (5% slower at 2040^2); order 8 (T = 2) gains at most 13% on
-// small grids and loses from 640^2, so blocking is used for orders 2 and 4.
+// Eight steps per launch (halo H = T*M of 8 points at order 2, 16 at order
+// 4).  Measured against one step per launch (the tuned one-step kernel, 201
+// steps, a source and 200 receivers): order 2 is 2.4x faster on
+// 121^2..400^2 grids and 1.6-1.8x on 1040^2..1500^2; order 4 1.7-1.8x on
+// 121^2..400^2 and 1.15-1.25x on 1040^2..1500^2.  Sixteen steps at order 2
+// and four at order 4 were slower (by up to 9% and 10%); order 8 (two steps,
+// halo 8) gained at most 13% on small grids and lost from 640^2, so
+// blocking is used for orders 2 and 4.
 template <int M>
-constexpr int tb_T() { return M == 1 ? 8 : M == 2 ? 4 : 1; }
+constexpr int tb_T() { return M <= 2 ? 8 : 1; }
 
 struct TbGeo {
     int32_t nz, nx;
