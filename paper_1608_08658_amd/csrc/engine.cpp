@@ -414,12 +414,12 @@ awe_status Plan::init(const awe_geometry* geo, hipStream_t setup, bool timed) {
         if ((st = upload(&d_fold_cells, wide))) return st;
         n_fold_cells = (int32_t)wide.size();
     }
-    // blocked 2-D steps (orders 2 and 4, grids up to 3M points: where they
-    // beat one step per launch): receivers by tile of their lowest node, and
-    // two more fields
-    constexpr int64_t kTbMaxPoints = 3000000;
+    // blocked 2-D steps where they beat one step per launch (measured: order
+    // 2 up to 2500^2 = 6.25M points and beyond, order 4 up to 1500^2 but not
+    // from 1800^2): receivers by tile of their lowest node, and two more fields
+    const int64_t tb_max_points = half == 1 ? 8000000 : 2500000;
     const char* tb_env = std::getenv("AWE_TB");
-    if (g.ndim == 2 && tb_steps(half) > 1 && L.points() <= kTbMaxPoints && fuse_sparse &&
+    if (g.ndim == 2 && tb_steps(half) > 1 && L.points() <= tb_max_points && fuse_sparse &&
         !(tb_env && tb_env[0] == '0') && src_csr.nrows <= kFuseMaxNodes &&
         (src_csr.nrows == 0 || src_zyx)) {
         const int64_t tile = tb_tile(), gxn = (L.n[2] + tile - 1) / tile, gzn = (L.n[0] + tile - 1) / tile;

@@ -27,8 +27,9 @@ constexpr int kTbGroup = 4;          // rows per thread evaluated together
 // Eight steps per launch (halo H = T*M of 8 points at order 2, 16 at order
 // 4).  Measured against one step per launch (the tuned one-step kernel, 201
 // steps, a source and 200 receivers): order 2 is 2.4x faster on
-// 121^2..400^2 grids and 1.6-1.8x on 1040^2..1500^2; order 4 1.7-1.8x on
-// 121^2..400^2 and 1.15-1.25x on 1040^2..1500^2.  Sixteen steps at order 2
+// 121^2..400^2 grids and 1.4-1.8x on 1040^2..2500^2; order 4 1.7-1.8x on
+// 121^2..400^2 and 1.15-1.25x on 1040^2..1500^2 but slower from 1800^2 (the
+// plan limits blocking by grid size accordingly).  Sixteen steps at order 2
 // and four at order 4 were slower (by up to 9% and 10%); order 8 (two steps,
 // halo 8) gained at most 13% on small grids and lost from 640^2, so
 // blocking is used for orders 2 and 4.
