@@ -60,6 +60,17 @@ def test_footprint_grows_with_checkpoints():
     assert per_field >= (40 + 16) * (50 + 16) * 4
 
 
+def test_footprint_counts_the_fields_of_the_forward():
+    # C and the two wavefields, plus two work fields in 2-D (blocked steps)
+    g2 = _geom()
+    pts2 = (40 + 16) * (50 + 16)
+    assert awe.footprint(g2, 0) >= 5 * 4 * pts2
+    g3 = _geom(shape=(30, 40, 50), spacing=(10.0, 10.0, 10.0), src_coords=[[100.0, 100.0, 100.0]],
+               rec_coords=[[50.0, 50.0, 50.0]])
+    pts3 = (30 + 16) * (40 + 16) * (50 + 16)
+    assert 3 * 4 * pts3 <= awe.footprint(g3, 0) < 5 * 4 * pts3 * 1.5
+
+
 @pytest.mark.parametrize("bad", [
     dict(space_order=5), dict(space_order=18), dict(shape=(1, 50)), dict(spacing=(0.0, 10.0)),
     dict(dt=-1.0), dict(nt=0), dict(nbl=-1), dict(src_coords=[[-200.0, 0.0]]),
