@@ -1,5 +1,6 @@
 """The continuous-batching shot server: results in the mix equal results alone,
-admission respects the memory budget, and a bad request fails alone."""
+admission respects the memory budget, a bad request fails alone, and
+degenerate requests (one sample, no sources, no receivers) complete."""
 import numpy as np
 import pytest
 
@@ -111,4 +112,35 @@ def test_oversized_request_is_rejected_at_submit(monkeypatch):
     with pytest.raises(awe.AweError) as e:
         srv.submit(_geom(s, dt), s.m, w)
     assert e.value.status == -2
+    srv.close()
+
+
+def test_degenerate_requests_complete():
+    # one sample (no step), no sources, no receivers, from a 2-D and a 3-D
+    # request, all in one server: each completes, with traces of its shape,
+    # zero where no step is taken or nothing is injected
+    import paper_1608_08658_amd as awe
+    base = _requests(51, 2, scale=0.1)
+    srv = awe.Server(hbm_fraction=0.5, chunk_steps=4, max_active=4)
+    cases = []
+    for shot, dt, w in base:
+        one_shot = synth.Shot(shot.name + "-nt1", shot.shape, shot.spacing, shot.order, shot.nbl, 1, shot.m,
+                              shot.src_coords, shot.rec_coords, shot.f0, damp_vref=shot.damp_vref)
+        cases.append((one_shot, dt, w[:1]))
+        nosrc = synth.Shot(shot.name + "-nosrc", shot.shape, shot.spacing, shot.order, shot.nbl, 9, shot.m,
+                           np.zeros((0, len(shot.shape))), shot.rec_coords, shot.f0, damp_vref=shot.damp_vref)
+        cases.append((nosrc, dt, np.zeros((9, 0), np.float32)))
+        norec = synth.Shot(shot.name + "-norec", shot.shape, shot.spacing, shot.order, shot.nbl, 9, shot.m,
+                           shot.src_coords, np.zeros((0, len(shot.shape))), shot.f0, damp_vref=shot.damp_vref)
+        cases.append((norec, dt, w[:9]))
+    tickets = []
+    for shot, dt, w in cases:
+        tickets.append(srv.submit(_geom(shot, dt), shot.m, w))
+    for (t, _), (shot, _, _) in zip(tickets, cases):
+        srv.wait(t, timeout=120)
+        assert srv.poll(t)[0] == 2, shot.name
+    for (t, tr), (shot, dt, w) in zip(tickets, cases):
+        assert tr.shape == (shot.nt, len(shot.rec_coords)), shot.name
+        if shot.nt == 1 or len(shot.src_coords) == 0:
+            assert np.all(tr == 0.0), shot.name
     srv.close()
