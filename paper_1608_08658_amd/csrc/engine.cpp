@@ -19,6 +19,7 @@
 #include "awe.h"
 #include "awe_internal.hpp"
 #include "engine.hpp"
+#include "tune_policy.hpp"
 
 namespace awe {
 
@@ -579,22 +580,9 @@ awe_status Plan::tune(bool img, hipStream_t user_stream) {
             if (e == hipSuccess) best_of[i] = std::min(best_of[i], ms);
         }
     }
-    // Candidates within 1% of the fastest are a tie at this timing's noise;
-    // of those, the longest z-chunk (fewest warm-up planes re-read), then
-    // the faster.  Without this, near-equal shapes flip from plan to plan.
-    float fastest = 1e30f;
-    for (size_t i = 0; i < cand.size(); ++i) fastest = std::min(fastest, best_of[i]);
-    LaunchShape best = shape;
-    float best_ms = 1e30f;
-    int best_zc = -1;
-    for (size_t i = 0; i < cand.size(); ++i) {
-        if (!(best_of[i] <= 1.01f * fastest)) continue;
-        if (cand[i].zchunk > best_zc || (cand[i].zchunk == best_zc && best_of[i] < best_ms)) {
-            best = cand[i];
-            best_zc = cand[i].zchunk;
-            best_ms = best_of[i];
-        }
-    }
+    // near-equal timings are a tie, settled by the longest z-chunk (tune_policy.hpp)
+    const int pick = pick_timed_shape(cand.size(), best_of.data(), [&](size_t i) { return cand[i].zchunk; });
+    const LaunchShape best = pick >= 0 ? cand[pick] : shape;
     if (e != hipSuccess) st = fail(AWE_EHIP, "autotune: %s", hipGetErrorString(e));
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);

@@ -1,0 +1,72 @@
+// CPU checks of the autotuner's choice of launch shape (tune_policy.hpp):
+// fixed cases (a clear winner, ties settled by the longer z-chunk and then
+// the faster, the tie boundary, nothing timed) and seeded random timings
+// checked against the properties that define the choice.  Prints "ok" or
+// the failed check and exits non-zero on failure.
+#include <cstdio>
+#include <random>
+#include <vector>
+
+#include "tune_policy.hpp"
+
+static int fails = 0;
+#define CHECK(c)                                                   \
+    do {                                                           \
+        if (!(c)) {                                                \
+            std::printf("FAILED: %s (line %d)\n", #c, __LINE__);   \
+            ++fails;                                               \
+        }                                                          \
+    } while (0)
+
+static int pick(const std::vector<float>& t, const std::vector<int>& zc) {
+    return awe::pick_timed_shape(t.size(), t.data(), [&](size_t i) { return zc[i]; });
+}
+
+int main() {
+    // a clear winner (other candidates more than 1% slower) whatever its chunk
+    CHECK(pick({110.f, 100.f, 120.f}, {56, 8, 84}) == 1);
+    // within 1%: the longer chunk
+    CHECK(pick({100.f, 100.5f, 103.f}, {42, 56, 84}) == 1);
+    // within 1% and equal chunks: the faster
+    CHECK(pick({100.8f, 100.f, 100.4f}, {56, 56, 42}) == 1);
+    // the boundary: exactly 1% slower is a tie, more is not
+    CHECK(pick({100.f, 101.f}, {8, 56}) == 1);
+    CHECK(pick({100.f, 101.2f}, {8, 56}) == 0);
+    // nothing timed (or nothing at all)
+    CHECK(pick({1e30f, 1e30f}, {8, 56}) == -1);
+    CHECK(pick({}, {}) == -1);
+    // untimed candidates never win
+    CHECK(pick({1e30f, 100.f, 1e30f}, {84, 8, 84}) == 1);
+
+    std::mt19937 rng(7);
+    std::uniform_real_distribution<float> time(100.f, 104.f);
+    const int chunks[] = {8, 14, 21, 28, 42, 56, 70, 84};
+    for (int it = 0; it < 20000; ++it) {
+        const int n = 1 + (int)(rng() % 40);
+        std::vector<float> t(n);
+        std::vector<int> zc(n);
+        for (int i = 0; i < n; ++i) {
+            t[i] = (rng() % 10 == 0) ? 1e30f : time(rng);
+            zc[i] = chunks[rng() % 8];
+        }
+        const int k = pick(t, zc);
+        float fastest = 1e30f;
+        for (float v : t) fastest = v < fastest ? v : fastest;
+        if (fastest >= 1e29f) {
+            CHECK(k == -1);
+            continue;
+        }
+        CHECK(k >= 0 && k < n);
+        if (k < 0 || k >= n) continue;
+        CHECK(t[k] <= 1.01f * fastest);               // a tie with the fastest
+        for (int i = 0; i < n; ++i) {
+            if (!(t[i] <= 1.01f * fastest)) continue;
+            CHECK(zc[i] <= zc[k]);                    // no tied shape has a longer chunk
+            if (zc[i] == zc[k]) CHECK(t[k] <= t[i]);  // and among equal chunks it is the fastest
+        }
+        if (fails) break;
+    }
+    if (fails) return 1;
+    std::printf("ok\n");
+    return 0;
+}
