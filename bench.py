@@ -397,7 +397,8 @@ def main():
     ap.add_argument("--born", type=int, default=1, help="time Born modelling on the forward grid (0 = skip)")
     ap.add_argument("--small-2d", type=int, default=1, help="time the small 2-D shot (0 = skip)")
     ap.add_argument("--serve-requests", type=int, default=200, help="requests per serving point (0 = skip)")
-    ap.add_argument("--serve-scale", type=float, default=0.5, help="size/step scale of the serving mix")
+    ap.add_argument("--serve-scale", type=float, default=1.0,
+                    help="size/step scale of the serving mix (1 = the full mix; < 1 shrinks it for quick runs)")
     ap.add_argument("--served-gradient-shots", type=int, default=32,
                     help="shots of the 300^3 served-gradient workload (0 = skip; 32 is the full workload)")
     ap.add_argument("--copy-ref-mb", type=int, default=0,

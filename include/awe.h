@@ -207,10 +207,33 @@ awe_status awe_forward_binomial(awe_plan plan, const float* wavelet_dev, float* 
  * it needs the preceding awe_forward on this plan to have used
  * ckpt_every > 0, or an awe_forward_binomial not yet used by a gradient
  * (else AWE_ESTATE).  Forward states are recomputed from the stored ones
- * during the sweep.
+ * during the sweep.  Afterwards the plan's wavefield state (awe_get_state)
+ * is the zero pair; periodic checkpoints stay valid for another gradient.
  */
 awe_status awe_adjoint(awe_plan plan, const float* resid_dev, float* src_adj_dev,
                        float* grad_m_dev, awe_stream stream);
+
+/*
+ * The forward state a gradient reads is the model of awe_set_model, the
+ * states stored by the last awe_forward / awe_forward_binomial and its
+ * wavelet (Eq. 3 pairs the adjoint field with the forward field of the same
+ * model and source).  *id_host receives an identifier of that state; it
+ * changes with every awe_set_model, awe_forward, awe_forward_binomial and
+ * awe_born on the plan, and when a gradient consumes binomial states.  A
+ * caller that keeps a forward for a later gradient (an autograd graph) takes
+ * the identifier right after that forward and passes it to
+ * awe_adjoint_checked.  Pure host function.
+ */
+awe_status awe_forward_id(awe_plan plan, int64_t* id_host);
+
+/*
+ * awe_adjoint, after checking that the plan still holds the forward state
+ * forward_id (awe_forward_id): AWE_ESTATE, before any work is enqueued, if
+ * another forward, model or linearised run has replaced it since.  F^T
+ * (grad_m_dev NULL) is checked too, since it depends on the model.
+ */
+awe_status awe_adjoint_checked(awe_plan plan, int64_t forward_id, const float* resid_dev, float* src_adj_dev,
+                               float* grad_m_dev, awe_stream stream);
 
 /*
  * Linearised (Born) modelling: traces_dev [nt][nrec] = J dm, the derivative

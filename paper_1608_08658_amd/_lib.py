@@ -50,6 +50,8 @@ _SIGNATURES = {
     "awe_forward": (_I32, [_P, _P, _P, _I32, _P]),
     "awe_forward_binomial": (_I32, [_P, _P, _P, _I32, _P]),
     "awe_adjoint": (_I32, [_P, _P, _P, _P, _P]),
+    "awe_forward_id": (_I32, [_P, C.POINTER(_I64)]),
+    "awe_adjoint_checked": (_I32, [_P, _I64, _P, _P, _P, _P]),
     "awe_born": (_I32, [_P, _P, _P, _P, _P]),
     "awe_get_gradient_padded": (_I32, [_P, _P, _P]),
     "awe_set_state": (_I32, [_P, _P, _P, _P]),

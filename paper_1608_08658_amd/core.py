@@ -179,13 +179,26 @@ class Plan:
             check(lib().awe_forward(self.handle, w, tr, int(ckpt_every), _stream()))
         return traces
 
-    def adjoint(self, resid, want_src_adj=True, want_grad=False):
+    def forward_id(self):
+        """Identifier of the forward state a gradient would read (changes with
+        every set_model, forward and born, and when binomial states are used)."""
+        out = C.c_int64()
+        check(lib().awe_forward_id(self.handle, C.byref(out)))
+        return out.value
+
+    def adjoint(self, resid, want_src_adj=True, want_grad=False, forward_id=None):
+        """F^T resid and, with ``want_grad``, the gradient.  ``forward_id``
+        (from :meth:`forward_id` after the forward) makes the call fail with
+        AWE_ESTATE if the plan no longer holds that forward."""
         torch = _torch()
         src_adj = torch.empty((self.nt, self.nsrc), dtype=torch.float32, device="cuda") if want_src_adj else None
         grad = torch.empty(self.shape, dtype=torch.float32, device="cuda") if want_grad else None
-        check(lib().awe_adjoint(self.handle, _ptr(resid, "resid", (self.nt, self.nrec)),
-                                _ptr(src_adj, "src_adj", allow_none=True), _ptr(grad, "grad", allow_none=True),
-                                _stream()))
+        args = (_ptr(resid, "resid", (self.nt, self.nrec)), _ptr(src_adj, "src_adj", allow_none=True),
+                _ptr(grad, "grad", allow_none=True), _stream())
+        if forward_id is None:
+            check(lib().awe_adjoint(self.handle, *args))
+        else:
+            check(lib().awe_adjoint_checked(self.handle, int(forward_id), *args))
         return src_adj, grad
 
     def born(self, wavelet, dm, traces=None):
@@ -238,13 +251,16 @@ def _make_gradient_fn():
             else:
                 traces = plan.forward(wavelet.contiguous(), ckpt_every=ckpt_every if need_m else 0)
             ctx.plan = plan
+            ctx.forward_id = plan.forward_id()
             return traces
 
         @staticmethod
         def backward(ctx, grad_traces):
+            # the plan holds one forward state: a later forward on it makes
+            # this backward fail (AWE_ESTATE) instead of differentiating that one
             plan = ctx.plan
             src_adj, grad = plan.adjoint(grad_traces.contiguous(), want_src_adj=ctx.needs_input_grad[1],
-                                         want_grad=ctx.needs_input_grad[0])
+                                         want_grad=ctx.needs_input_grad[0], forward_id=ctx.forward_id)
             return grad, src_adj, None, None, None
 
     return Gradient

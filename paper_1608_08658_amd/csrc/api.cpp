@@ -149,6 +149,22 @@ awe_status awe_adjoint(awe_plan plan, const float* resid, float* src_adj, float*
     AWE_TRY(return plan->adjoint(resid, src_adj, grad_m, as_stream(s)));
 }
 
+awe_status awe_forward_id(awe_plan plan, int64_t* id) {
+    if (!plan || !id) return fail(AWE_EINVAL, "NULL argument");
+    *id = plan->fwd_id;
+    return AWE_OK;
+}
+
+awe_status awe_adjoint_checked(awe_plan plan, int64_t forward_id, const float* resid, float* src_adj, float* grad_m,
+                               awe_stream s) {
+    if (!plan) return fail(AWE_EINVAL, "plan is NULL");
+    if (forward_id != plan->fwd_id)
+        return fail(AWE_ESTATE, "the plan no longer holds forward state %lld (now %lld): another forward, model "
+                                "or linearised run replaced it",
+                    (long long)forward_id, (long long)plan->fwd_id);
+    AWE_TRY(return plan->adjoint(resid, src_adj, grad_m, as_stream(s)));
+}
+
 awe_status awe_born(awe_plan plan, const float* wavelet, const float* dm, float* traces, awe_stream s) {
     if (!plan) return fail(AWE_EINVAL, "plan is NULL");
     AWE_TRY(return plan->born(wavelet, dm, traces, as_stream(s)));

@@ -142,6 +142,18 @@ std::vector<int> stored_times(int nt, int K) {
 
 int segment_slots(int nt, int K) { return std::max(0, std::min(K - 1, nt - 1)); }
 
+// Upper bound on the source's grid nodes (its CSR rows): 2^d per source.
+static int64_t src_node_bound(const awe_geometry* g) { return (int64_t)g->nsrc << g->ndim; }
+
+bool tb_candidate(const awe_geometry* g, const Layout& L, int64_t src_nodes) {
+    const int half = g->space_order / 2;
+    const int64_t tb_max_points = half == 1 ? 8000000 : 2500000;
+    return g->ndim == 2 && tb_steps(half) > 1 && L.points() <= tb_max_points && src_nodes <= kFuseMaxNodes;
+}
+
+// Every device byte a plan for g holds after a forward (K = 0) or after a
+// gradient with checkpoints every K steps: the admission test of the server
+// relies on this bounding the plan's allocations.
 uint64_t footprint_bytes(const awe_geometry* g, int K) {
     int64_t pad[3], phys[3];
     padded_zyx(g, pad, phys);
@@ -150,10 +162,19 @@ uint64_t footprint_bytes(const awe_geometry* g, int K) {
     const int corners = 1 << g->ndim;
     uint64_t b = 3 * field;                                                    // C, two wavefields
     b += (uint64_t)(pad[0] + pad[1] + pad[2]) * 12;                            // eta tables (fp32 + fp64)
+    // point tables (node int64 + weight fp32) and the two CSR tables (node,
+    // row start, point, weight), all with 2^d entries per point
     b += (uint64_t)(g->nsrc + g->nrec) * corners * (8 + 4) * 2 + 8 * corners * (g->nsrc + g->nrec + 2);
-    b += 64 * 1024;                                                            // reduction scratch
-    if (g->ndim == 2)                                                          // blocked steps: two more fields
-        b += 2 * field + (uint64_t)g->nrec * 12 + (uint64_t)(pad[0] / 64 + 2) * (pad[2] / 64 + 2) * 4;
+    if (src_node_bound(g) <= kFuseMaxNodes) b += (uint64_t)src_node_bound(g) * 3 * 4;   // source node (z, y, x)
+    b += (uint64_t)fold_wide_cells(g->ndim, phys, g->nbl).size() * 8;          // gradient fold's wide cells
+    b += 3 * 4096 * 4 + (kReduceBlocks + 1) * 8;                               // reduction partials
+    if (tb_candidate(g, L, 0)) {
+        // blocked steps (whenever the grid allows them, so the bound also
+        // holds where the sources rule them out): two more fields, receivers'
+        // base nodes and tile lists
+        const int64_t t = tb_tile();
+        b += 2 * field + (uint64_t)g->nrec * 12 + (uint64_t)((pad[0] + t - 1) / t * ((pad[2] + t - 1) / t) + 1) * 4;
+    }
     if (K > 0) {
         b += (uint64_t)(stored_times(g->nt, K).size() + segment_slots(g->nt, K) + 3) * field;  // + mu x2, g
         b += (uint64_t)g->nt * g->nsrc * 4;                                    // wavelet copy
@@ -418,10 +439,8 @@ awe_status Plan::init(const awe_geometry* geo, hipStream_t setup, bool timed) {
     // blocked 2-D steps where they beat one step per launch (measured: order
     // 2 up to 2500^2 = 6.25M points and beyond, order 4 up to 1500^2 but not
     // from 1800^2): receivers by tile of their lowest node, and two more fields
-    const int64_t tb_max_points = half == 1 ? 8000000 : 2500000;
     const char* tb_env = std::getenv("AWE_TB");
-    if (g.ndim == 2 && tb_steps(half) > 1 && L.points() <= tb_max_points && fuse_sparse &&
-        !(tb_env && tb_env[0] == '0') && src_csr.nrows <= kFuseMaxNodes &&
+    if (tb_candidate(&g, L, src_csr.nrows) && fuse_sparse && !(tb_env && tb_env[0] == '0') &&
         (src_csr.nrows == 0 || src_zyx)) {
         const int64_t tile = tb_tile(), gxn = (L.n[2] + tile - 1) / tile, gzn = (L.n[0] + tile - 1) / tile;
         std::vector<int32_t> zx(2 * (size_t)g.nrec), ptr(gxn * gzn + 1, 0), list(g.nrec), tile_of(g.nrec);
@@ -617,6 +636,7 @@ awe_status Plan::set_model(const float* m, hipStream_t s) {
     model_set = true;
     have_ckpt = false;
     have_grad = false;
+    ++fwd_id;
     return AWE_OK;
 }
 
@@ -781,6 +801,7 @@ awe_status Plan::forward(const float* wavelet, float* traces, int K, hipStream_t
     if (K < 0) return fail(AWE_EINVAL, "ckpt_every must be >= 0");
     awe_status st;
     have_ckpt = false;
+    ++fwd_id;
     if (K > 0) {
         if ((st = ensure_gradient_storage(K))) return st;
         if (g.nsrc > 0)
@@ -829,6 +850,7 @@ awe_status Plan::forward_binomial(const float* wavelet, float* traces, int snaps
     if (g.nsrc > 0 && !wavelet) return fail(AWE_EINVAL, "wavelet is NULL but nsrc > 0");
     if (snapshots < 0) return fail(AWE_EINVAL, "snapshots must be >= 0");
     have_ckpt = false;
+    ++fwd_id;
     awe_status st;
     if ((st = ensure_binomial_storage(snapshots))) return st;
     if (g.nsrc > 0)
@@ -905,6 +927,7 @@ awe_status Plan::born(const float* wavelet, const float* dm_phys, float* traces,
     for (float* f : {w0, w1, b_du0, b_du1}) AWE_HIP(launch_fill(f, L.total, 0.f, s));
     float* const tr = (traces && g.nrec > 0) ? traces : nullptr;
     have_ckpt = false;
+    ++fwd_id;
     cur = w0;
     prev = w1;
     float* dcur = b_du0;     // du[n]
@@ -1023,6 +1046,7 @@ awe_status Plan::adjoint(const float* resid, float* src_adj, float* grad_phys, h
         AWE_HIP(launch_fold(grad_phys, grad, L, phys, g.nbl, (float)(-1.0 / (g.dt * g.dt)), d_fold_cells, n_fold_cells, s));
         cur = prev = zero;   // the wavefield state no longer holds u[nt-1]
         have_ckpt = false;
+        ++fwd_id;            // the stored states are consumed
         have_grad = true;
         return AWE_OK;
     }
@@ -1056,6 +1080,9 @@ awe_status Plan::adjoint(const float* resid, float* src_adj, float* grad_phys, h
     }
     // g_phys = fold(-(1/dt^2) * accumulated imaging)
     AWE_HIP(launch_fold(grad_phys, grad, L, phys, g.nbl, (float)(-1.0 / (g.dt * g.dt)), d_fold_cells, n_fold_cells, s));
+    // w0 served as the zero field: the wavefield state is now (0, 0), as after
+    // a binomial gradient (the stored states stay valid for another gradient)
+    cur = prev = zero;
     have_grad = true;
     return AWE_OK;
 }

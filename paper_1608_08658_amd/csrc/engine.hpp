@@ -25,6 +25,9 @@ Layout make_layout(int ndim, const int64_t pad[3], int half);
 std::vector<int> stored_times(int nt, int K);
 int segment_slots(int nt, int K);
 uint64_t footprint_bytes(const awe_geometry* g, int K);
+// The static conditions under which a 2-D plan advances several forward
+// steps per launch (the plan also needs few enough receivers per tile).
+bool tb_candidate(const awe_geometry* g, const Layout& L, int64_t src_nodes);
 
 struct LaunchShape {
     int cfg;        // workgroup shape (see launch_step)
@@ -209,6 +212,9 @@ struct awe_plan_s {
     int rev_snaps = -1;             // snapshots of the schedule in rev (-1: none)
     bool rev_mode = false;          // the stored states are binomial (else periodic)
     bool have_ckpt = false, have_grad = false;
+    // Changes whenever the forward state a gradient reads (model, stored
+    // states, wavelet copy) is replaced or consumed (awe_forward_id).
+    int64_t fwd_id = 0;
 
     ~awe_plan_s();
     awe_status init(const awe_geometry* geo, hipStream_t setup = nullptr, bool timed = true);

@@ -73,3 +73,42 @@ def small_2d_shot(seed, order, shape=(150, 170), nbl=10, nt=300, nrec=41, f0=15.
     rec = np.column_stack([np.full(nrec, 25.0), np.linspace(0, span[1], nrec)])
     return synth.Shot(f"small2d-o{order}", shape, h, order, nbl, nt, 1.0 / v ** 2, src, rec, f0,
                       dt_factor=0.5, damp_power=1, damp_vref=float(v.min()))
+
+
+def oracle_block(op, lo, hi, nt=None, backend="numpy"):
+    """The oracle operator ``op`` restricted to the padded-grid block
+    [lo, hi): update coefficients sliced, node indices shifted, and only the
+    sources and receivers whose nodes all lie inside the block kept.  Returns
+    (block operator, kept source indices, kept receiver indices).
+
+    Its fields equal the full operator's wherever nothing outside the block
+    reaches them: callers place every source and receiver that can influence
+    the block inside it and size the block so that no field reaches its
+    faces within nt steps (the stencil spreads M points per step).  backend
+    "c" takes the oracle's C time step (bit-identical to NumPy, faster)."""
+    import copy
+    sl = tuple(slice(a, b) for a, b in zip(lo, hi))
+    p = copy.copy(op.p)
+    p.padded_shape = tuple(b - a for a, b in zip(lo, hi))
+    if nt is not None:
+        p.nt = int(nt)
+    sub = object.__new__(oracle.Operator)
+    sub.p = p
+    sub.backend = backend
+    sub.A, sub.B, sub.C = op.A[sl], op.B[sl], op.C[sl]
+    sub.vol = op.vol
+    lo_a, hi_a = np.asarray(lo), np.asarray(hi)
+
+    def restrict(table):
+        if table is None:
+            return None, np.zeros(0, dtype=np.int64)
+        nodes, w = table
+        inside = np.all((nodes >= lo_a) & (nodes < hi_a), axis=(1, 2))
+        idx = np.nonzero(inside)[0]
+        if idx.size == 0:
+            return None, idx
+        return (nodes[idx] - lo_a, w[idx]), idx
+
+    sub.src, src_idx = restrict(op.src)
+    sub.rec, rec_idx = restrict(op.rec)
+    return sub, src_idx, rec_idx

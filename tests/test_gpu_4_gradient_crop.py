@@ -48,4 +48,4 @@ def test_order16_gradient_crop_2000_steps():
     assert e_tr <= 1e-4
     assert e_op <= 1e-4
     assert e_phi <= 2e-5 * kappa
-    assert e_g <= 1e-4 + 1e-5 * kappa
+    assert e_g <= 1e-4

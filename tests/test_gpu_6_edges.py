@@ -196,3 +196,27 @@ def test_several_sources_sharing_cells():
     log(f"case 4 sources: traces {e_tr:.2e}, F^T {e_sa:.2e}, gradient {e_g:.2e}")
     assert e_tr <= 1e-4 and e_sa <= 1e-4 and e_g <= 1e-4
     assert np.array_equal(out["src_adj"][:, 0], out["src_adj"][:, 1])
+
+
+@pytest.mark.parametrize("kind,order,K", [("2d", 4, 10), ("3d", 8, 7), ("3d", 16, 30)])
+def test_footprint_bounds_plan_memory(kind, order, K):
+    # The server admits requests by awe_footprint: it must bound what a plan
+    # holds after a forward and after a checkpointed gradient (2-D order 4 is
+    # a blocked-step plan with two more fields and tile lists).  After a
+    # periodic gradient the wavefield state is the zero pair.
+    import paper_1608_08658_amd as awe
+    shot = small_2d_shot(960 + order, order, nt=60) if kind == "2d" else small_3d_shot(960 + order, order, nt=60)
+    dt = shot_dt(shot)
+    plan = gpu_plan(shot, dt)
+    plan.set_model(dev(shot.m))
+    w = dev(shot.wavelet(dt))
+    tr = plan.forward(w)
+    held0, fp0 = plan.info()["bytes"], awe.footprint(plan.geom, 0)
+    tr = plan.forward(w, ckpt_every=K)
+    plan.adjoint(tr, want_src_adj=True, want_grad=True)
+    held1, fp1 = plan.info()["bytes"], awe.footprint(plan.geom, K)
+    log(f"case {shot.name} K={K}: forward holds {held0} of {fp0} B, gradient {held1} of {fp1} B")
+    assert held0 <= fp0 and held1 <= fp1
+    u, up = plan.get_state()
+    assert not np.any(host(u)) and not np.any(host(up))
+    plan.close()
