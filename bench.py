@@ -137,6 +137,27 @@ def bench_gradient(torch, awe, synth, n=400, nt=2000, snapshots=20):
     f1.record()
     torch.cuda.synchronize()
     t_fwd = f0.elapsed_time(f1) / 1e3
+    # Per-kernel durations from HIP events on the launching stream around
+    # every 4th launch of one more (untimed) gradient: the stencil step
+    # without imaging (forward with the receivers sampled inside, and the
+    # recomputation), the adjoint step with imaging, and the residual
+    # injection launched on its own.
+    plan.time_kernels(4)
+    gradient(events())
+    kt = plan.kernel_times()
+    plan.time_kernels(0)
+    kernels = {}
+    for kind, nbytes in (("step", BYTES_PER_UPDATE), ("imaging", 28.0)):
+        cnt, us = kt[kind]
+        if cnt:
+            gbs = nbytes * npad / (us * 1e-6) / 1e9
+            kernels[kind] = {"launches_timed": cnt, "avg_launch_us": us, "bytes_per_update": nbytes,
+                             "achieved_GBps": gbs, "frac": gbs / HBM_PEAK_GBS}
+    if kt["points"][0]:
+        kernels["points"] = {"launches_timed": kt["points"][0], "avg_launch_us": kt["points"][1]}
+    log("gradient kernels: " + ", ".join(f"{k} {v['avg_launch_us']:.1f} us" +
+                                          (f" ({100 * v['frac']:.1f}% of peak)" if "frac" in v else "")
+                                          for k, v in kernels.items()))
     info = plan.info()
     finite = bool(torch.isfinite(g).all().item())
     binomial = None
@@ -180,7 +201,7 @@ def bench_gradient(torch, awe, synth, n=400, nt=2000, snapshots=20):
         "gradient_algorithmic_GBps": 60.0 * upd / t_grad / 1e9,
         "device_bytes": info["bytes"], "launch_shapes": {"forward": info["forward_shape"],
                                                          "imaging": info["imaging_shape"]},
-        "finite": finite, "binomial": binomial,
+        "kernels": kernels, "finite": finite, "binomial": binomial,
     }
 
 

@@ -160,6 +160,22 @@ awe_status awe_plan_destroy(awe_plan plan);
 awe_status awe_plan_info(awe_plan plan, int64_t* out_host);
 
 /*
+ * Launch timing for measurement: with every > 0, the plan records a HIP
+ * event pair on the launching stream around every every-th stencil step
+ * launch and every every-th point-operator launch of its forward, step,
+ * recompute and adjoint sweeps (awe_born and launch-shape tuning are not
+ * timed); every == 0 switches it off.  Each call clears what was recorded.
+ * awe_plan_kernel_times waits for the recorded launches and writes
+ * out_host[0..5] = (count, mean microseconds) for stencil steps without
+ * imaging (forward and recompute, the point operators inside included when
+ * they run in the same launch), stencil steps with imaging (the gradient's
+ * adjoint), and point operators launched on their own.  The events add
+ * nothing to the launches they bracket but a timestamp each.
+ */
+awe_status awe_plan_time_kernels(awe_plan plan, int32_t every);
+awe_status awe_plan_kernel_times(awe_plan plan, double* out_host);
+
+/*
  * Load the physical model m_dev (physical shape, squared slowness) and build
  * the update coefficients on the padded grid (the layer copies the nearest
  * edge cell of the model).  Checks that m is finite and positive and that

@@ -46,6 +46,8 @@ _SIGNATURES = {
     "awe_plan_create": (_I32, [C.POINTER(Geometry), C.POINTER(_P)]),
     "awe_plan_destroy": (_I32, [_P]),
     "awe_plan_info": (_I32, [_P, C.POINTER(_I64)]),
+    "awe_plan_time_kernels": (_I32, [_P, _I32]),
+    "awe_plan_kernel_times": (_I32, [_P, C.POINTER(_D)]),
     "awe_set_model": (_I32, [_P, _P, _P]),
     "awe_forward": (_I32, [_P, _P, _P, _I32, _P]),
     "awe_forward_binomial": (_I32, [_P, _P, _P, _I32, _P]),

@@ -161,6 +161,17 @@ class Plan:
         return {"padded": tuple(out[:self.ndim]), "bytes": out[3], "forward_shape": (out[4], out[5]),
                 "imaging_shape": (out[6], out[7])}
 
+    def time_kernels(self, every=1):
+        """Record HIP events around every ``every``-th step launch (0: off)."""
+        check(lib().awe_plan_time_kernels(self.handle, int(every)))
+
+    def kernel_times(self):
+        """{kind: (launches timed, mean microseconds)} for 'step' (no imaging),
+        'imaging' and 'points' (point operators launched on their own)."""
+        out = (C.c_double * 6)()
+        check(lib().awe_plan_kernel_times(self.handle, out))
+        return {k: (int(out[2 * i]), out[2 * i + 1]) for i, k in enumerate(("step", "imaging", "points"))}
+
     def set_model(self, m):
         check(lib().awe_set_model(self.handle, _ptr(m, "m", self.shape), _stream()))
 

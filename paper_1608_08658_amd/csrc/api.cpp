@@ -128,6 +128,19 @@ awe_status awe_plan_info(awe_plan plan, int64_t* out) {
     return AWE_OK;
 }
 
+awe_status awe_plan_time_kernels(awe_plan plan, int32_t every) {
+    if (!plan) return fail(AWE_EINVAL, "plan is NULL");
+    if (every < 0) return fail(AWE_EINVAL, "every must be >= 0");
+    plan->timer_reset();
+    plan->timer_every = every;
+    return AWE_OK;
+}
+
+awe_status awe_plan_kernel_times(awe_plan plan, double* out) {
+    if (!plan || !out) return fail(AWE_EINVAL, "NULL argument");
+    AWE_TRY(return plan->kernel_times(out));
+}
+
 awe_status awe_set_model(awe_plan plan, const float* m, awe_stream s) {
     if (!plan) return fail(AWE_EINVAL, "plan is NULL");
     AWE_TRY(return plan->set_model(m, as_stream(s)));

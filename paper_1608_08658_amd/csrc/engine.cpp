@@ -345,6 +345,36 @@ void Plan::release(void* p) {
 
 Plan::~awe_plan_s() {
     for (auto& o : owned) (void)hipFree(o.first);
+    timer_reset();
+    for (auto& pr : timer_free) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+}
+
+void Plan::timer_reset() {
+    for (auto& t : timer_pending) timer_free.push_back({t.a, t.b});
+    timer_pending.clear();
+    for (int i = 0; i < 3; ++i) timer_seen[i] = timer_count[i] = 0, timer_ms[i] = 0.0;
+}
+
+// Waits for the recorded launches and returns, per kind, the number timed
+// and their mean duration in microseconds (out[2k], out[2k+1]).
+awe_status Plan::kernel_times(double* out) {
+    for (auto& t : timer_pending) {
+        AWE_HIP(hipEventSynchronize(t.b));
+        float ms = 0.f;
+        AWE_HIP(hipEventElapsedTime(&ms, t.a, t.b));
+        timer_ms[t.kind] += ms;
+        ++timer_count[t.kind];
+        timer_free.push_back({t.a, t.b});
+    }
+    timer_pending.clear();
+    for (int k = 0; k < 3; ++k) {
+        out[2 * k] = (double)timer_count[k];
+        out[2 * k + 1] = timer_count[k] ? 1e3 * timer_ms[k] / (double)timer_count[k] : 0.0;
+    }
+    return AWE_OK;
 }
 
 // All set-up work runs on `setup` and init waits for that stream only, so a
@@ -685,11 +715,11 @@ awe_status Plan::advance(const float* uc, const float* up, float* out, const flo
         fs.inj = inj;
         fs.inj_zyx = src_zyx;
         fs.smp = smp;
-        AWE_HIP(launch_step(L, k, a, kStepPlain, fwd_shape.cfg, fwd_shape.zchunk, s, &fs));
+        AWE_HIP(timed(0, s, [&] { return launch_step(L, k, a, kStepPlain, fwd_shape.cfg, fwd_shape.zchunk, s, &fs); }));
         return AWE_OK;
     }
-    AWE_HIP(launch_step(L, k, a, kStepPlain, fwd_shape.cfg, fwd_shape.zchunk, s));
-    AWE_HIP(launch_sparse(inj, smp, s));
+    AWE_HIP(timed(0, s, [&] { return launch_step(L, k, a, kStepPlain, fwd_shape.cfg, fwd_shape.zchunk, s); }));
+    AWE_HIP(timed(2, s, [&] { return launch_sparse(inj, smp, s); }));
     return AWE_OK;
 }
 
@@ -992,7 +1022,7 @@ awe_status Plan::adjoint(const float* resid, float* src_adj, float* grad_phys, h
         const bool img = usnap != nullptr;
         StepArgs a{m1, m2, m2, coef, d_ez, d_ey, d_ex, usnap, img ? grad : nullptr};
         const LaunchShape& sh = img ? img_shape : fwd_shape;
-        AWE_HIP(launch_step(L, k, a, img ? kStepImaging : kStepPlain, sh.cfg, sh.zchunk, s));
+        AWE_HIP(timed(img ? 1 : 0, s, [&] { return launch_step(L, k, a, img ? kStepImaging : kStepPlain, sh.cfg, sh.zchunk, s); }));
         InjectOp inj;
         if (g.nrec > 0) {
             inj.field = m2;
@@ -1016,7 +1046,7 @@ awe_status Plan::adjoint(const float* resid, float* src_adj, float* grad_phys, h
             smp.npts = g.nsrc;
             smp.corners = corners;
         }
-        AWE_HIP(launch_sparse(inj, smp, s));
+        AWE_HIP(timed(2, s, [&] { return launch_sparse(inj, smp, s); }));
         std::swap(m1, m2);
         return AWE_OK;
     };

@@ -216,6 +216,22 @@ struct awe_plan_s {
     // states, wavelet copy) is replaced or consumed (awe_forward_id).
     int64_t fwd_id = 0;
 
+    // Optional timing of the step launches (awe_plan_time_kernels): HIP
+    // events on the launching stream around every `timer_every`-th launch of
+    // each kind (0: stencil steps without imaging, 1: with imaging, 2: point
+    // operators launched on their own), resolved by kernel_times().
+    int timer_every = 0;
+    int64_t timer_seen[3] = {0, 0, 0};
+    double timer_ms[3] = {0, 0, 0};
+    int64_t timer_count[3] = {0, 0, 0};
+    struct TimedLaunch { int kind; hipEvent_t a, b; };
+    std::vector<TimedLaunch> timer_pending;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> timer_free;
+    template <class F>
+    hipError_t timed(int kind, hipStream_t s, F&& launch);
+    awe_status kernel_times(double* out);
+    void timer_reset();
+
     ~awe_plan_s();
     awe_status init(const awe_geometry* geo, hipStream_t setup = nullptr, bool timed = true);
     awe_status set_model(const float* m, hipStream_t s);
@@ -246,4 +262,24 @@ struct awe_plan_s {
 
 namespace awe {
 using Plan = awe_plan_s;
+}
+
+template <class F>
+hipError_t awe_plan_s::timed(int kind, hipStream_t s, F&& launch) {
+    if (timer_every <= 0 || (timer_seen[kind]++ % timer_every) != 0 || timer_pending.size() >= 200000) return launch();
+    hipEvent_t a = nullptr, b = nullptr;
+    if (!timer_free.empty()) {
+        a = timer_free.back().first;
+        b = timer_free.back().second;
+        timer_free.pop_back();
+    } else {
+        hipError_t e = hipEventCreate(&a);
+        if (e == hipSuccess) e = hipEventCreate(&b);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipEventRecord(a, s);
+    if (e == hipSuccess) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(b, s);
+    timer_pending.push_back({kind, a, b});
+    return e;
 }
