@@ -259,53 +259,84 @@ def bench_serve(awe, synth, count=200, scale=0.5, seed=4, max_active=16, chunk=6
             "requests": count, "saturation": sat, "poisson": points}
 
 
-def bench_served_gradient(torch, awe, synth, n=300, nt=1500, nshots=32):
-    """Per-shot FWI gradients through the autograd Function, summed on the
-    device in fixed shot order, against a plain forward of the same shot."""
+def bench_served_gradient(torch, awe, synth, n=300, nt=1500, nshots=32, max_active=2):
+    """Served gradient requests: per-shot FWI gradients submitted to the shot
+    server (awe_server_submit_gradient: forward with checkpoints, misfit and
+    adjoint-state gradient, advanced in chunks), summed on the device in
+    fixed shot order (awe_sum_fields), timed from the first submission to the
+    summed gradient; against a plain forward of the same shot.  One shot is
+    repeated through the autograd Function, which gives the same bits."""
     shots = synth.config_served_gradient(n=n, nt=nt, nshots=nshots)
     K = shots[0].extra["checkpoint_every"]
     m_true = shots[0].extra["m_true"]
     vmax = float(np.sqrt(1.0 / min(shots[0].m.min(), m_true.min())))
     dt = shots[0].dt_factor * awe.dt_max(3, shots[0].order, shots[0].spacing, vmax)
-    m0 = torch.tensor(shots[0].m, dtype=torch.float32, device="cuda")
     mt = torch.tensor(m_true, dtype=torch.float32, device="cuda")
-    total = torch.zeros_like(m0)
+    m0_host = shots[0].m.astype(np.float32)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    t_grad, t_fwd = [], []
-    loss_sum = 0.0
+    geoms, wavelets, observed, t_fwd = [], [], [], []
     for i, sh in enumerate(shots):
+        g = awe.make_geometry(shape=sh.shape, spacing=sh.spacing, space_order=sh.order, nbl=sh.nbl, dt=dt, nt=sh.nt,
+                              src_coords=sh.src_coords, rec_coords=sh.rec_coords, damp_power=sh.damp_power,
+                              damp_R=sh.damp_R, damp_vref=sh.damp_vref)
+        w = sh.wavelet(dt).astype(np.float32)
         plan = awe.Plan(shape=sh.shape, spacing=sh.spacing, space_order=sh.order, nbl=sh.nbl, dt=dt, nt=sh.nt,
                         src_coords=sh.src_coords, rec_coords=sh.rec_coords, damp_power=sh.damp_power,
                         damp_R=sh.damp_R, damp_vref=sh.damp_vref)
-        w = torch.tensor(sh.wavelet(dt), dtype=torch.float32, device="cuda")
         plan.set_model(mt)
-        d_obs = plan.forward(w).clone()
-        m = m0.clone().requires_grad_(True)
+        wd = torch.tensor(w, device="cuda")
         ev[0].record()
-        tr = awe.Gradient.apply(m, w, plan, K)
-        loss = 0.5 * ((tr - d_obs) ** 2).sum()
-        loss.backward()
-        total += m.grad
-        ev[1].record()
-        torch.cuda.synchronize()
-        t_grad.append(ev[0].elapsed_time(ev[1]) / 1e3)
-        loss_sum += float(loss.detach())
-        ev[0].record()
-        plan.forward(w)
+        d_obs = plan.forward(wd)
         ev[1].record()
         torch.cuda.synchronize()
         t_fwd.append(ev[0].elapsed_time(ev[1]) / 1e3)
-        plan.close()
-        log(f"shot {i + 1}/{len(shots)}: gradient {t_grad[-1]:.3f} s, forward {t_fwd[-1]:.3f} s")
+        geoms.append(g)
+        wavelets.append(w)
+        observed.append(d_obs.cpu().numpy())
+        if i < len(shots) - 1:     # the last shot's plan serves the autograd check
+            plan.close()
+    log(f"served gradients: {len(shots)} observed shots modelled, forward {np.median(t_fwd):.3f} s per shot")
+    grads = [torch.empty(shots[0].shape, dtype=torch.float32, device="cuda") for _ in shots]
+    srv = awe.Server(hbm_fraction=0.9, chunk_steps=64, max_active=max_active)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    subs = [srv.submit_gradient(geoms[i], m0_host, wavelets[i], observed[i], K, grads[i], want_traces=False)
+            for i in range(len(shots))]
+    for t, _, _ in subs:
+        srv.wait(t, timeout=900)
+    times = np.array([srv.poll(t)[1] for t, _, _ in subs])
+    total = awe.sum_fields(grads)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    srv.close()
+    lat = times[:, 3] - times[:, 0]
+    svc = times[:, 3] - times[:, 2]
+    phi = float(sum(p[0] for _, _, p in subs))
+    # the autograd path on the last shot: the same gradient bit for bit
+    sh = shots[-1]
+    m = torch.tensor(m0_host, device="cuda").requires_grad_(True)
+    tr = awe.Gradient.apply(m, torch.tensor(wavelets[-1], device="cuda"), plan, K)
+    loss = 0.5 * ((tr - torch.tensor(observed[-1], device="cuda")) ** 2).sum()
+    loss.backward()
+    same = bool(torch.equal(m.grad, grads[-1]))
+    plan.close()
     npad = (n + 80) ** 3
-    tg, tf = float(np.median(t_grad[1:] or t_grad)), float(np.median(t_fwd[1:] or t_fwd))
-    return {"workload": f"{nshots} shots on one {n}^3 layered model with an anomaly (+40-point layer), order 8, "
-                        f"{nt} samples, checkpoints every {K} steps, 4x8 surface sources, "
-                        f"{len(shots[0].rec_coords)} receivers, gradients via the autograd Function summed on device",
-            "shots": nshots, "total_gradient_s": float(sum(t_grad)), "median_gradient_s": tg,
-            "median_forward_s": tf, "gradient_over_forward": tg / tf, "algorithmic_gradient_over_forward": 3.75,
-            "gradient_algorithmic_GBps": 60.0 * npad * (nt - 1) / tg / 1e9,
-            "total_misfit": loss_sum, "gradient_finite": bool(torch.isfinite(total).all().item())}
+    tf = float(np.median(t_fwd))
+    per_shot = wall / len(shots)
+    log(f"served gradients: {len(shots)} requests in {wall:.2f} s ({per_shot:.3f} s per shot, "
+        f"{per_shot / tf:.2f}x the forward), p50 latency {np.percentile(lat, 50):.2f} s, "
+        f"autograd path bitwise equal: {same}")
+    return {"workload": f"{nshots} gradient requests on one {n}^3 layered model with an anomaly (+40-point layer), "
+                        f"order 8, {nt} samples, checkpoints every {K} steps, 4x8 surface sources, "
+                        f"{len(shots[0].rec_coords)} receivers, served (up to {max_active} running), "
+                        f"gradients summed on device in shot order",
+            "shots": nshots, "max_active": max_active, "total_gradient_s": wall, "gradient_s_per_shot": per_shot,
+            "median_service_s": float(np.median(svc)), "p50_latency_s": float(np.percentile(lat, 50)),
+            "p99_latency_s": float(np.percentile(lat, 99)), "median_forward_s": tf,
+            "gradient_over_forward": per_shot / tf, "algorithmic_gradient_over_forward": 3.75,
+            "gradient_algorithmic_GBps": 60.0 * npad * (nt - 1) / per_shot / 1e9,
+            "total_misfit": phi, "autograd_equals_served": same,
+            "gradient_finite": bool(torch.isfinite(total).all().item())}
 
 
 def bench_born(torch, awe, synth, n=256, nt=1000):

@@ -35,6 +35,10 @@
  *     before any work is enqueued.
  *   - Threading: a plan is not re-entrant; different plans may be used from
  *     different threads on different streams.
+ *   - Devices: a plan or a server lives on the HIP device that is current on
+ *     the calling thread when it is created (hipSetDevice); calls that
+ *     enqueue work on a plan must be made with that device current
+ *     (AWE_EINVAL otherwise).
  */
 #ifndef AWE_H
 #define AWE_H
@@ -96,7 +100,7 @@ const char* awe_version(void);
 
 /*
  * Weights c_0..c_M (M = order/2) of the central second derivative of even
- * order `order` on a unit grid (Sec. IV.A.1; for order 2 they are -2, 1).
+ * order `order` on a unit grid (Sec. IV.A, derivative expressions; for order 2 they are -2, 1).
  * w_host must hold M+1 doubles.  Pure host function.
  */
 awe_status awe_fd_weights(int32_t order, double* w_host);
@@ -118,7 +122,7 @@ awe_status awe_footprint(const awe_geometry* g, int32_t ckpt_every, uint64_t* by
 /*
  * Binomial checkpointing (Griewank 1992; Griewank & Walther 2000, the
  * "revolve" schedule): the alternative to a stored full history of the
- * forward wavefield that the paper names as under evaluation (Sec. IV.B.4).
+ * forward wavefield that the paper names as under evaluation (Sec. IV.B, memory mapping).
  * The gradient's reverse sweep (Eqs. 3-4) visits the states
  * (u[t], u[t-1]), t = nt-1 .. 0; with `snapshots` stored states the schedule
  * takes the fewest forward steps that any schedule with that many stored
@@ -143,7 +147,7 @@ awe_status awe_footprint_binomial(const awe_geometry* g, int32_t snapshots, uint
  * which its set-up runs).  For 3-D grids of 4M points and more and 2-D grids
  * of 64K points and more, the first plan of a grid size times the stencil's
  * launch shapes on its own buffers (the paper's block-size autotuning,
- * Sec. IV.B.3; tens to hundreds of launches) unless a shape for the same
+ * Sec. IV.B, loop blocking; tens to hundreds of launches) unless a shape for the same
  * order and size (3-D: a size within 30% in points) is already known in the
  * process;
  * the environment variables AWE_TILE=cfg,zchunk and AWE_AUTOTUNE=0 pin or
@@ -176,11 +180,15 @@ awe_status awe_plan_time_kernels(awe_plan plan, int32_t every);
 awe_status awe_plan_kernel_times(awe_plan plan, double* out_host);
 
 /*
- * Load the physical model m_dev (physical shape, squared slowness) and build
- * the update coefficients on the padded grid (the layer copies the nearest
- * edge cell of the model).  Checks that m is finite and positive and that
- * dt <= awe_dt_max(max speed): otherwise AWE_EUNSTABLE.  Synchronises
- * `stream` (it reads the model's extrema back to the host).
+ * Load the physical model m_dev (physical shape, squared slowness: the `m`
+ * of Eq. 1 and Listing 1) and build the update coefficients on the padded
+ * grid: the absorbing layer of nbl points on every side (Sec. V.D pads the
+ * 201 x 201 x 70 model with 40 points per side) copies the nearest edge cell
+ * of the model, and the layer's damping is the `damp` term of Listing 1
+ * (profile: awe_geometry's damp_power, damp_R, damp_vref).  Checks that m is
+ * finite and positive and that dt <= awe_dt_max(max speed): otherwise
+ * AWE_EUNSTABLE.  Synchronises `stream` (it reads the model's extrema back
+ * to the host).
  */
 awe_status awe_set_model(awe_plan plan, const float* m_dev, awe_stream stream);
 
@@ -291,11 +299,24 @@ awe_status awe_get_state(awe_plan plan, float* u_dev, float* u_prev_dev, awe_str
 awe_status awe_misfit(const float* traces_dev, const float* d_obs_dev, int64_t n,
                       float* resid_dev, double* phi_host, awe_stream stream);
 
+/*
+ * Sum over shots: out_dev[i] = sum_{p=0}^{nparts-1} parts_host[p][i] for
+ * i < n, accumulated in FP64 in the order p = 0, 1, ... and rounded once to
+ * FP32.  The misfit of Eq. 2 over several shots is the sum of theirs, so its
+ * gradient is the sum of the per-shot gradients; summing in a fixed order
+ * makes the result independent of the order in which the shots finished.
+ * parts_host is a host array of nparts (1..64) device pointers to FP32
+ * arrays of n values; out_dev may be one of them.
+ */
+awe_status awe_sum_fields(float* out_dev, const float* const* parts_host, int32_t nparts, int64_t n,
+                          awe_stream stream);
+
 /* ---------------------------------------------------------------------------
  * Serving: a shot server with continuous batching on the current device.
- * Requests carry their own geometry, model and wavelet (host memory, copied
- * at submit).  An engine thread admits queued requests in arrival order
- * while the sum of their awe_footprint stays within hbm_fraction of the
+ * Requests (forward shots, or gradients) carry their own geometry, model
+ * and wavelet (host memory, copied at submit).  An engine thread admits
+ * queued requests in arrival order while the sum of their awe_footprint
+ * stays within hbm_fraction of the
  * device memory that was free at creation and at most max_active run at
  * once.  Each running request advances on its own stream in chunks of
  * chunk_steps time steps, two chunks in flight, independently of the others
@@ -313,10 +334,27 @@ enum { AWE_REQ_QUEUED = 0, AWE_REQ_RUNNING = 1, AWE_REQ_DONE = 2, AWE_REQ_FAILED
 
 awe_status awe_server_create(double hbm_fraction, int32_t chunk_steps, int32_t max_active,
                              awe_server* out);
-/* Copies g (and its coordinates), m_host (physical shape) and wavelet_host
- * ([nt][nsrc]).  Returns a ticket >= 0.  Non-blocking. */
+/* A forward request.  Copies g (and its coordinates), m_host (physical
+ * shape) and wavelet_host ([nt][nsrc]).  Returns a ticket >= 0.
+ * Non-blocking. */
 awe_status awe_server_submit(awe_server srv, const awe_geometry* g, const float* m_host,
                              const float* wavelet_host, float* traces_host, int64_t* ticket);
+/*
+ * A gradient request (Eqs. 2-3): the forward with checkpoints every
+ * ckpt_every steps, the misfit against d_obs_host ([nt][nrec], copied at
+ * submit) and the adjoint-state gradient, each advanced in chunks among the
+ * other requests' work with the arithmetic of awe_forward, awe_misfit and
+ * awe_adjoint on a plan run alone (so the results equal theirs bit for bit).
+ * Its footprint (awe_footprint with ckpt_every, plus inputs and traces) is
+ * admitted against the budget like any request.  When the request is done,
+ * grad_dev (device memory on the server's device, physical shape, kept by
+ * the caller until then) holds the gradient with respect to m, *phi_host
+ * the misfit and traces_host ([nt][nrec]) the modelled traces; phi_host and
+ * traces_host may be NULL.  Returns a ticket >= 0.  Non-blocking.
+ */
+awe_status awe_server_submit_gradient(awe_server srv, const awe_geometry* g, const float* m_host,
+                                      const float* wavelet_host, const float* d_obs_host, int32_t ckpt_every,
+                                      float* traces_host, float* grad_dev, double* phi_host, int64_t* ticket);
 /* state = AWE_REQ_*; times_host[4] = (submit, admit, start, done) in seconds
  * on the server's monotonic clock (-1 where not reached yet).  For a failed
  * request *state is AWE_REQ_FAILED and awe_last_error() holds its message. */

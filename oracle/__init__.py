@@ -14,7 +14,7 @@ the adjoint dot-product test (Eqs. 5-6), finite-difference and Taylor tests
 of the gradient (Eqs. 7-8), and checkpointed == full-storage gradients.
 
 Modules
-  fd        weights (exact rationals) and the Laplacian       Sec. IV.A.1
+  fd        weights (exact rationals) and the Laplacian       Sec. IV.A
   medium    padding, damping, update coefficients, CFL          Sec. V.C, V.D
   sparse    source injection / receiver interpolation           Sec. IV
   wave      forward, adjoint, misfit, gradient, checkpointing   Sec. V.A, Eqs. 1-4

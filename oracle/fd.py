@@ -4,7 +4,7 @@ rationals and FP64.
 Test infrastructure: part of the plain CPU oracle.  Only the test-suite, the
 smoke check and the CPU-baseline leg of the benchmark use it.
 
-The paper (Sec. IV.A.1, "Derivative expressions") sets the accuracy of the
+The paper (Sec. IV.A, "Derivative expressions") sets the accuracy of the
 second derivative by one parameter, ``space_order``, and prints the order-2
 case: f.dx2 = (f(x-h) - 2 f(x) + f(x+h)) / h^2.  For a general even order
 P = 2M the symmetric (2M+1)-point stencil is *defined* here as the one that
@@ -15,7 +15,7 @@ M+1 even-moment equations
     sum_{k=-M..M} c_|k| k^j = 2 [j == 2],   j = 0, 2, ..., 2M,
 
 which this module solves by exact Gaussian elimination over the rationals.
-The Laplacian (Sec. IV.A.1, the ``laplace`` shorthand; the 3-D form printed
+The Laplacian (Sec. IV.A, derivative expressions, the ``laplace`` shorthand; the 3-D form printed
 as ``f.dx2 + f.dy2 + f.dz`` is read as ``... + f.dz2``) is the sum of the
 per-axis second derivatives, with the field taken as zero outside the array
 (the untouched outer halo of the generated code in Listing 3).

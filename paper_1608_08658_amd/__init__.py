@@ -7,7 +7,8 @@ The compute path is libawe.so (hand-written HIP for gfx950) behind the C ABI
 of include/awe.h; this package only marshals arguments to it.
 """
 from ._lib import AweError, header_symbols, lib
-from .core import Gradient, Plan, Server, binomial_cost, dt_max, fd_weights, footprint, make_geometry, misfit
+from .core import (Gradient, Plan, Server, binomial_cost, dt_max, fd_weights, footprint, make_geometry, misfit,
+                   sum_fields)
 
 __all__ = ["AweError", "Gradient", "Plan", "Server", "binomial_cost", "dt_max", "fd_weights", "footprint", "make_geometry",
-           "misfit", "header_symbols", "lib"]
+           "misfit", "sum_fields", "header_symbols", "lib"]

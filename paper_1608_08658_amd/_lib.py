@@ -62,6 +62,9 @@ _SIGNATURES = {
     "awe_misfit": (_I32, [_P, _P, _I64, _P, C.POINTER(_D), _P]),
     "awe_server_create": (_I32, [_D, _I32, _I32, C.POINTER(_P)]),
     "awe_server_submit": (_I32, [_P, C.POINTER(Geometry), _P, _P, _P, C.POINTER(_I64)]),
+    "awe_server_submit_gradient": (_I32, [_P, C.POINTER(Geometry), _P, _P, _P, _I32, _P, _P, C.POINTER(_D),
+                                          C.POINTER(_I64)]),
+    "awe_sum_fields": (_I32, [_P, C.POINTER(_P), _I32, _I64, _P]),
     "awe_server_poll": (_I32, [_P, _I64, C.POINTER(_I32), C.POINTER(_D)]),
     "awe_server_wait": (_I32, [_P, _I64, _D]),
     "awe_server_stats": (_I32, [_P, C.POINTER(_I64)]),

@@ -15,7 +15,7 @@ from . import _lib
 from ._lib import AweError, Geometry, check, lib
 
 __all__ = ["Plan", "Server", "Gradient", "make_geometry", "fd_weights", "dt_max", "footprint", "misfit",
-           "AweError"]
+           "sum_fields", "AweError"]
 
 
 def _torch():
@@ -110,6 +110,21 @@ def binomial_cost(nt: int, snapshots: int) -> tuple[int, int]:
     steps, fields = C.c_int64(), C.c_int32()
     check(lib().awe_binomial_cost(int(nt), int(snapshots), C.byref(steps), C.byref(fields)))
     return steps.value, fields.value
+
+
+def sum_fields(parts, out=None):
+    """Sum of equally shaped device tensors in list order, accumulated in FP64
+    and rounded once (deterministic whatever order they were produced in)."""
+    torch = _torch()
+    if not parts:
+        raise ValueError("no parts")
+    if out is None:
+        out = torch.empty_like(parts[0])
+    ptrs = (C.c_void_p * len(parts))(*[_ptr(p, f"parts[{i}]", tuple(parts[0].shape)).value
+                                       for i, p in enumerate(parts)])
+    check(lib().awe_sum_fields(_ptr(out, "out", tuple(parts[0].shape)), ptrs, len(parts), parts[0].numel(),
+                               _stream()))
+    return out
 
 
 def misfit(traces, d_obs, want_resid=True):
@@ -309,6 +324,26 @@ class Server:
                                       C.c_void_p(traces.ctypes.data), C.byref(t)))
         self._keep[t.value] = (traces, geom)
         return t.value, traces
+
+    def submit_gradient(self, geom: GeometryHolder, m: np.ndarray, wavelet: np.ndarray, d_obs: np.ndarray,
+                        ckpt_every: int, grad, want_traces=True):
+        """A gradient request: copies m, wavelet [nt, nsrc] and d_obs [nt, nrec]
+        (host, float32); the gradient lands in ``grad`` (a device tensor of the
+        physical shape, kept alive here until the request is done).  Returns
+        (ticket, traces array or None, phi array of one value)."""
+        g = geom.g
+        m = np.ascontiguousarray(m, dtype=np.float32)
+        w = np.ascontiguousarray(wavelet, dtype=np.float32).reshape(g.nt, g.nsrc)
+        obs = np.ascontiguousarray(d_obs, dtype=np.float32).reshape(g.nt, g.nrec)
+        traces = np.zeros((g.nt, g.nrec), dtype=np.float32) if want_traces else None
+        phi = np.full(1, np.nan, dtype=np.float64)
+        t = C.c_int64()
+        check(lib().awe_server_submit_gradient(
+            self._h, C.byref(g), C.c_void_p(m.ctypes.data), C.c_void_p(w.ctypes.data), C.c_void_p(obs.ctypes.data),
+            int(ckpt_every), C.c_void_p(traces.ctypes.data) if traces is not None else None,
+            _ptr(grad, "grad", geom.shape), phi.ctypes.data_as(C.POINTER(C.c_double)), C.byref(t)))
+        self._keep[t.value] = (traces, phi, grad, geom)
+        return t.value, traces, phi
 
     def poll(self, ticket):
         st = C.c_int32()

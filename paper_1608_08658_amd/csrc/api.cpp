@@ -26,6 +26,17 @@ using awe::fail;
 
 static inline hipStream_t as_stream(awe_stream s) { return reinterpret_cast<hipStream_t>(s); }
 
+// A plan lives on the device that was current when it was created; calls that
+// enqueue work on it must be made with that device current.
+#define AWE_PLAN(plan)                                                                              \
+    do {                                                                                            \
+        if (!(plan)) return fail(AWE_EINVAL, "plan is NULL");                                       \
+        int d_ = -1;                                                                                \
+        if (hipGetDevice(&d_) != hipSuccess || d_ != (plan)->device)                                \
+            return fail(AWE_EINVAL, "the plan was created on device %d but device %d is current",  \
+                        (plan)->device, d_);                                                        \
+    } while (0)
+
 extern "C" {
 
 const char* awe_last_error(void) { return awe::t_err.c_str(); }
@@ -142,23 +153,23 @@ awe_status awe_plan_kernel_times(awe_plan plan, double* out) {
 }
 
 awe_status awe_set_model(awe_plan plan, const float* m, awe_stream s) {
-    if (!plan) return fail(AWE_EINVAL, "plan is NULL");
+    AWE_PLAN(plan);
     AWE_TRY(return plan->set_model(m, as_stream(s)));
 }
 
 awe_status awe_forward(awe_plan plan, const float* wavelet, float* traces, int32_t ckpt_every, awe_stream s) {
-    if (!plan) return fail(AWE_EINVAL, "plan is NULL");
+    AWE_PLAN(plan);
     AWE_TRY(return plan->forward(wavelet, traces, ckpt_every, as_stream(s)));
 }
 
 awe_status awe_forward_binomial(awe_plan plan, const float* wavelet, float* traces, int32_t snapshots,
                                 awe_stream s) {
-    if (!plan) return fail(AWE_EINVAL, "plan is NULL");
+    AWE_PLAN(plan);
     AWE_TRY(return plan->forward_binomial(wavelet, traces, snapshots, as_stream(s)));
 }
 
 awe_status awe_adjoint(awe_plan plan, const float* resid, float* src_adj, float* grad_m, awe_stream s) {
-    if (!plan) return fail(AWE_EINVAL, "plan is NULL");
+    AWE_PLAN(plan);
     AWE_TRY(return plan->adjoint(resid, src_adj, grad_m, as_stream(s)));
 }
 
@@ -170,7 +181,7 @@ awe_status awe_forward_id(awe_plan plan, int64_t* id) {
 
 awe_status awe_adjoint_checked(awe_plan plan, int64_t forward_id, const float* resid, float* src_adj, float* grad_m,
                                awe_stream s) {
-    if (!plan) return fail(AWE_EINVAL, "plan is NULL");
+    AWE_PLAN(plan);
     if (forward_id != plan->fwd_id)
         return fail(AWE_ESTATE, "the plan no longer holds forward state %lld (now %lld): another forward, model "
                                 "or linearised run replaced it",
@@ -179,19 +190,21 @@ awe_status awe_adjoint_checked(awe_plan plan, int64_t forward_id, const float* r
 }
 
 awe_status awe_born(awe_plan plan, const float* wavelet, const float* dm, float* traces, awe_stream s) {
-    if (!plan) return fail(AWE_EINVAL, "plan is NULL");
+    AWE_PLAN(plan);
     AWE_TRY(return plan->born(wavelet, dm, traces, as_stream(s)));
 }
 
 awe_status awe_get_gradient_padded(awe_plan plan, float* g_pad, awe_stream s) {
-    if (!plan || !g_pad) return fail(AWE_EINVAL, "NULL argument");
+    AWE_PLAN(plan);
+    if (!g_pad) return fail(AWE_EINVAL, "NULL argument");
     if (!plan->have_grad) return fail(AWE_ESTATE, "no gradient has been computed on this plan");
     AWE_HIP(awe::launch_pack(g_pad, plan->grad, plan->L, (float)(-1.0 / (plan->g.dt * plan->g.dt)), as_stream(s)));
     return AWE_OK;
 }
 
 awe_status awe_set_state(awe_plan plan, const float* u, const float* u_prev, awe_stream s) {
-    if (!plan || !u || !u_prev) return fail(AWE_EINVAL, "NULL argument");
+    AWE_PLAN(plan);
+    if (!u || !u_prev) return fail(AWE_EINVAL, "NULL argument");
     AWE_HIP(awe::launch_unpack(plan->w0, u, plan->L, as_stream(s)));
     AWE_HIP(awe::launch_unpack(plan->w1, u_prev, plan->L, as_stream(s)));
     plan->cur = plan->w0;
@@ -200,14 +213,25 @@ awe_status awe_set_state(awe_plan plan, const float* u, const float* u_prev, awe
 }
 
 awe_status awe_step(awe_plan plan, int32_t n0, int32_t nsteps, const float* wavelet, float* traces, awe_stream s) {
-    if (!plan) return fail(AWE_EINVAL, "plan is NULL");
+    AWE_PLAN(plan);
     AWE_TRY(return plan->step(n0, nsteps, wavelet, traces, as_stream(s)));
 }
 
 awe_status awe_get_state(awe_plan plan, float* u, float* u_prev, awe_stream s) {
-    if (!plan) return fail(AWE_EINVAL, "plan is NULL");
+    AWE_PLAN(plan);
     if (u) AWE_HIP(awe::launch_pack(u, plan->cur, plan->L, 1.f, as_stream(s)));
     if (u_prev) AWE_HIP(awe::launch_pack(u_prev, plan->prev, plan->L, 1.f, as_stream(s)));
+    return AWE_OK;
+}
+
+awe_status awe_sum_fields(float* out, const float* const* parts, int32_t nparts, int64_t n, awe_stream s) {
+    if (!out || !parts) return fail(AWE_EINVAL, "NULL argument");
+    if (nparts < 1 || nparts > awe::kMaxSumParts)
+        return fail(AWE_EINVAL, "nparts must be in 1..%d (got %d)", awe::kMaxSumParts, nparts);
+    if (n < 0) return fail(AWE_EINVAL, "n must be >= 0");
+    for (int q = 0; q < nparts; ++q)
+        if (!parts[q]) return fail(AWE_EINVAL, "parts[%d] is NULL", q);
+    AWE_HIP(awe::launch_sum_parts(out, parts, nparts, n, as_stream(s)));
     return AWE_OK;
 }
 

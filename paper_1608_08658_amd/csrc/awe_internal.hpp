@@ -155,6 +155,10 @@ hipError_t launch_unpack(float* pitched, const float* dense, const Layout& L, hi
 hipError_t launch_misfit(const float* tr, const float* obs, int64_t n, float* resid, double* partial,
                          int blocks, double* result, hipStream_t s);
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);
+constexpr int kMaxSumParts = 64;
+// out[i] = sum of parts[0..nparts-1][i] in that order, FP64, one rounding
+// (parts: host array of device pointers, nparts <= kMaxSumParts).
+hipError_t launch_sum_parts(float* out, const float* const* parts, int nparts, int64_t n, hipStream_t s);
 constexpr int kReduceBlocks = 1024;
 
 }  // namespace awe

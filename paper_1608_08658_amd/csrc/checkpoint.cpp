@@ -3,7 +3,7 @@
 // The adjoint sweep (Eq. 4) visits the forward states x_t = (u[t], u[t-1])
 // in reverse order, t = nt-1 .. 0, and the imaging condition (Eq. 3) needs
 // u[t] at visit t.  Keeping every state is what the paper's memory-mapped
-// full history does (Sec. IV.B.4, which names other forms of checkpointing as
+// full history does (Sec. IV.B, memory-mapping paragraph, which names other forms of checkpointing as
 // the alternative under study).  Periodic checkpoints (every K steps) cut
 // memory to ~nt/K + K fields at one extra forward sweep.  The binomial
 // schedule of Griewank (1992, "Achieving logarithmic growth of temporal and

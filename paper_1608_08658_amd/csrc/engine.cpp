@@ -42,7 +42,7 @@ awe_status fail(awe_status code, const char* fmt, ...) {
     } while (0)
 
 // ---------------------------------------------------------------------------
-// FD weights (Sec. IV.A.1): central second derivative of order P = 2M,
+// FD weights (Sec. IV.A, derivative expressions): central second derivative of order P = 2M,
 //   c_k = 2 (-1)^(k+1) (M!)^2 / (k^2 (M-k)! (M+k)!),  c_0 = -2 sum_k c_k
 // (closed form of Fornberg, Math. Comp. 1988).  For M <= 8 numerator and
 // denominator are integers below 2^53, so each c_k is one correctly rounded
@@ -316,11 +316,13 @@ awe_status Plan::alloc(void** p, size_t bytes) {
     return AWE_OK;
 }
 
-awe_status Plan::alloc_field(float** p) {
+// A wavefield-sized buffer, zeroed once on stream s (the ghost cells must
+// stay zero for the plan's lifetime); work that uses it later on s is ordered
+// after the fill, so nothing waits for the device.
+awe_status Plan::alloc_field(float** p, hipStream_t s) {
     awe_status st = alloc((void**)p, (size_t)L.total * sizeof(float));
     if (st) return st;
-    // zero once: the ghost cells must stay zero for the plan's lifetime
-    AWE_HIP(launch_fill(*p, L.total, 0.f, setup_stream));
+    AWE_HIP(launch_fill(*p, L.total, 0.f, s));
     return AWE_OK;
 }
 
@@ -489,12 +491,14 @@ awe_status Plan::init(const awe_geometry* geo, hipStream_t setup, bool timed) {
             std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
             for (int r = 0; r < g.nrec; ++r) list[fill[tile_of[r]]++] = r;
             if ((st = upload(&d_rec_zx, zx)) || (st = upload(&d_tile_ptr, ptr)) || (st = upload(&d_tile_rec, list)) ||
-                (st = alloc_field(&w2)) || (st = alloc_field(&w3)))
+                (st = alloc_field(&w2, setup_stream)) || (st = alloc_field(&w3, setup_stream)))
                 return st;
             tb_T = tb_steps(half);
         }
     }
-    if ((st = alloc_field(&coef)) || (st = alloc_field(&w0)) || (st = alloc_field(&w1))) return st;
+    if ((st = alloc_field(&coef, setup_stream)) || (st = alloc_field(&w0, setup_stream)) ||
+        (st = alloc_field(&w1, setup_stream)))
+        return st;
     if ((st = alloc((void**)&d_partial, 3 * 4096 * sizeof(float)))) return st;
     if ((st = alloc((void**)&d_mpart, (kReduceBlocks + 1) * sizeof(double)))) return st;
     AWE_HIP(hipStreamSynchronize(setup_stream));
@@ -506,7 +510,7 @@ awe_status Plan::init(const awe_geometry* geo, hipStream_t setup, bool timed) {
 
 // ---------------------------------------------------------------------------
 // Launch-shape autotuning (the GPU counterpart of the paper's block-size
-// autotuning, Sec. IV.B.3): time each candidate workgroup shape and z-chunk
+// autotuning, Sec. IV.B, loop blocking): time each candidate workgroup shape and z-chunk
 // length on this plan's own buffers and keep the fastest.  Every shape
 // computes the same arithmetic per point, so the choice never changes results.
 // Results are cached per (device, dimensions, order, padded grid, kernel).
@@ -776,38 +780,37 @@ void Plan::release_binomial() {
 
 // Adjoint fields (mu pair, imaging accumulator) and the wavelet copy the
 // reverse sweep's recomputation injects.
-awe_status Plan::ensure_adjoint_storage() {
+awe_status Plan::ensure_adjoint_storage(hipStream_t s) {
     awe_status st;
-    if (!mu0 && ((st = alloc_field(&mu0)) || (st = alloc_field(&mu1)))) return st;
-    if (!grad && (st = alloc_field(&grad))) return st;
+    if (!mu0 && ((st = alloc_field(&mu0, s)) || (st = alloc_field(&mu1, s)))) return st;
+    if (!grad && (st = alloc_field(&grad, s))) return st;
     if (!wavelet_copy && g.nsrc > 0 && (st = alloc((void**)&wavelet_copy, (size_t)g.nt * g.nsrc * sizeof(float))))
         return st;
     return AWE_OK;
 }
 
-awe_status Plan::ensure_gradient_storage(int K) {
+awe_status Plan::ensure_gradient_storage(int K, hipStream_t s) {
     release_binomial();
     if (K == ckpt_K && storage_ready) return AWE_OK;
     release_periodic();
     awe_status st;
     for (int t : stored_times(g.nt, K)) {
         float* p = nullptr;
-        if ((st = alloc_field(&p))) return st;
+        if ((st = alloc_field(&p, s))) return st;
         stored[t] = p;
     }
     for (int i = 0; i < segment_slots(g.nt, K); ++i) {
         float* p = nullptr;
-        if ((st = alloc_field(&p))) return st;
+        if ((st = alloc_field(&p, s))) return st;
         slots.push_back(p);
     }
-    if ((st = ensure_adjoint_storage())) return st;
+    if ((st = ensure_adjoint_storage(s))) return st;
     ckpt_K = K;
-    AWE_HIP(hipDeviceSynchronize());
     storage_ready = true;
     return AWE_OK;
 }
 
-awe_status Plan::ensure_binomial_storage(int snapshots) {
+awe_status Plan::ensure_binomial_storage(int snapshots, hipStream_t s) {
     release_periodic();
     awe_status st;
     if (rev_snaps != snapshots) {
@@ -817,15 +820,18 @@ awe_status Plan::ensure_binomial_storage(int snapshots) {
     }
     while ((int)rev_pool.size() < rev.pool) {
         float* p = nullptr;
-        if ((st = alloc_field(&p))) return st;
+        if ((st = alloc_field(&p, s))) return st;
         rev_pool.push_back(p);
     }
-    if ((st = ensure_adjoint_storage())) return st;
-    AWE_HIP(hipDeviceSynchronize());
-    return AWE_OK;
+    return ensure_adjoint_storage(s);
 }
 
-awe_status Plan::forward(const float* wavelet, float* traces, int K, hipStream_t s) {
+// The forward of awe_forward in two parts so that a caller (the shot server)
+// can advance it a chunk of steps at a time: forward_begin sets up storage
+// and the zero initial state, forward_advance takes up to max_steps steps and
+// finishes the sweep after the last one.  The steps, their order and their
+// buffers do not depend on how the sweep is cut.
+awe_status Plan::forward_begin(const float* wavelet, float* traces, int K, hipStream_t s) {
     if (!model_set) return fail(AWE_ESTATE, "awe_set_model has not been called on this plan");
     if (g.nsrc > 0 && !wavelet) return fail(AWE_EINVAL, "wavelet is NULL but nsrc > 0");
     if (K < 0) return fail(AWE_EINVAL, "ckpt_every must be >= 0");
@@ -833,7 +839,7 @@ awe_status Plan::forward(const float* wavelet, float* traces, int K, hipStream_t
     have_ckpt = false;
     ++fwd_id;
     if (K > 0) {
-        if ((st = ensure_gradient_storage(K))) return st;
+        if ((st = ensure_gradient_storage(K, s))) return st;
         if (g.nsrc > 0)
             AWE_HIP(hipMemcpyAsync(wavelet_copy, wavelet, (size_t)g.nt * g.nsrc * sizeof(float),
                                    hipMemcpyDeviceToDevice, s));
@@ -842,19 +848,32 @@ awe_status Plan::forward(const float* wavelet, float* traces, int K, hipStream_t
     AWE_HIP(launch_fill(w1, L.total, 0.f, s));
     cur = w0;
     prev = w1;
+    fwd_job = FwdJob{wavelet, (traces && g.nrec > 0) ? traces : nullptr, K, 0, true};
+    return AWE_OK;
+}
+
+awe_status Plan::forward_advance(int max_steps, hipStream_t s, bool* done) {
+    FwdJob& j = fwd_job;
+    *done = false;
+    if (!j.active) return fail(AWE_ESTATE, "no forward sweep in progress");
+    awe_status st;
+    float* const tr = j.traces;
+    const float* const wavelet = j.wavelet;
     // Trace row n is recorded in the launch that injects into u[n+1]; row 0
     // samples u[0] = 0 and the last row follows the loop.
-    float* const tr = (traces && g.nrec > 0) ? traces : nullptr;
-    if (K == 0 && tb_T > 0) {
-        for (int n = 0; n + 1 < g.nt;) {
-            const int m = std::min(tb_T, g.nt - 1 - n);
-            if ((st = advance_tb(n, m, g.nsrc ? wavelet : nullptr, tr, 0, s))) return st;
-            n += m;
+    int budget = max_steps;
+    if (j.K == 0 && tb_T > 0) {
+        while (j.n + 1 < g.nt && budget > 0) {
+            const int m = std::min(tb_T, g.nt - 1 - j.n);
+            if ((st = advance_tb(j.n, m, g.nsrc ? wavelet : nullptr, tr, 0, s))) return st;
+            j.n += m;
+            budget -= m;
         }
     }
-    for (int n = 0; n + 1 < g.nt && !(K == 0 && tb_T > 0); ++n) {
+    for (; j.n + 1 < g.nt && budget > 0 && !(j.K == 0 && tb_T > 0); ++j.n, --budget) {
+        const int n = j.n;
         float* dst = nullptr;
-        if (K > 0) {
+        if (j.K > 0) {
             auto it = stored.find(n + 1);
             if (it != stored.end()) dst = it->second;
         }
@@ -865,10 +884,20 @@ awe_status Plan::forward(const float* wavelet, float* traces, int K, hipStream_t
         prev = cur;
         cur = dst;
     }
+    if (j.n + 1 < g.nt) return AWE_OK;
     if (tr) AWE_HIP(launch_sparse(InjectOp{}, rec_op(tr + (size_t)(g.nt - 1) * g.nrec, cur), s));
-    have_ckpt = K > 0;
+    have_ckpt = j.K > 0;
     rev_mode = false;
+    j.active = false;
+    *done = true;
     return AWE_OK;
+}
+
+awe_status Plan::forward(const float* wavelet, float* traces, int K, hipStream_t s) {
+    awe_status st = forward_begin(wavelet, traces, K, s);
+    bool done = false;
+    while (!st && !done) st = forward_advance(1 << 30, s, &done);
+    return st;
 }
 
 // The forward sweep of a binomial checkpointing schedule (checkpoint.cpp):
@@ -882,7 +911,7 @@ awe_status Plan::forward_binomial(const float* wavelet, float* traces, int snaps
     have_ckpt = false;
     ++fwd_id;
     awe_status st;
-    if ((st = ensure_binomial_storage(snapshots))) return st;
+    if ((st = ensure_binomial_storage(snapshots, s))) return st;
     if (g.nsrc > 0)
         AWE_HIP(hipMemcpyAsync(wavelet_copy, wavelet, (size_t)g.nt * g.nsrc * sizeof(float), hipMemcpyDeviceToDevice, s));
     AWE_HIP(launch_fill(w0, L.total, 0.f, s));   // x_0 = (0, 0)
@@ -950,8 +979,8 @@ awe_status Plan::born(const float* wavelet, const float* dm_phys, float* traces,
     if (!dm_phys) return fail(AWE_EINVAL, "dm is NULL");
     if (g.nsrc > 0 && !wavelet) return fail(AWE_EINVAL, "wavelet is NULL but nsrc > 0");
     awe_status st;
-    if (!b_t && ((st = alloc_field(&b_t)) || (st = alloc_field(&b_du0)) || (st = alloc_field(&b_du1)) ||
-                 (st = alloc_field(&b_dm))))
+    if (!b_t && ((st = alloc_field(&b_t, s)) || (st = alloc_field(&b_du0, s)) || (st = alloc_field(&b_du1, s)) ||
+                 (st = alloc_field(&b_dm, s))))
         return st;
     AWE_HIP(launch_pad(b_dm, dm_phys, L, phys, g.nbl, s));
     for (float* f : {w0, w1, b_du0, b_du1}) AWE_HIP(launch_fill(f, L.total, 0.f, s));
@@ -992,15 +1021,59 @@ awe_status Plan::born(const float* wavelet, const float* dm_phys, float* traces,
     return AWE_OK;
 }
 
-awe_status Plan::adjoint(const float* resid, float* src_adj, float* grad_phys, hipStream_t s) {
+// mu[n] from (mu[n+1], mu[n+2]) in place over mu[n+2], then one launch that
+// injects the residual row n into mu[n] and samples mu[n+1] (left untouched)
+// at the sources into row n of the adjoint source.  With usnap = u[n] the
+// step also accumulates the imaging condition.
+awe_status Plan::adj_step(int n, const float* usnap, hipStream_t s) {
+    AdjJob& j = adj_job;
+    const bool img = usnap != nullptr;
+    StepArgs a{j.m1, j.m2, j.m2, coef, d_ez, d_ey, d_ex, usnap, img ? grad : nullptr};
+    const LaunchShape& sh = img ? img_shape : fwd_shape;
+    AWE_HIP(timed(img ? 1 : 0, s, [&] { return launch_step(L, k, a, img ? kStepImaging : kStepPlain, sh.cfg, sh.zchunk, s); }));
+    InjectOp inj;
+    if (g.nrec > 0) {
+        inj.field = j.m2;
+        inj.coef = coef;
+        inj.node = rec_csr.node;
+        inj.rowptr = rec_csr.rowptr;
+        inj.pt = rec_csr.pt;
+        inj.w = rec_csr.w;
+        inj.values = j.resid + (size_t)n * g.nrec;
+        inj.usnap = usnap;
+        inj.grad = img ? grad : nullptr;
+        inj.nrows = rec_csr.nrows;
+    }
+    SampleOp smp;
+    if (j.src_adj && g.nsrc > 0 && n <= g.nt - 2) {
+        smp.out = j.src_adj + (size_t)n * g.nsrc;
+        smp.field = j.m1;
+        smp.node = src_node;
+        smp.w = src_w;
+        smp.scale = (float)(1.0 / vol);
+        smp.npts = g.nsrc;
+        smp.corners = corners;
+    }
+    AWE_HIP(timed(2, s, [&] { return launch_sparse(inj, smp, s); }));
+    std::swap(j.m1, j.m2);
+    return AWE_OK;
+}
+
+// The adjoint of awe_adjoint in two parts, like the forward: adjoint_begin
+// checks the state and clears the adjoint fields, adjoint_advance takes up
+// to max_steps steps (recomputed forward steps and adjoint steps both count)
+// and finishes the sweep after the last.  F^T alone and the periodic
+// checkpoint gradient resume where they stopped; a binomial gradient runs
+// its whole schedule in one call.
+awe_status Plan::adjoint_begin(const float* resid, float* src_adj, float* grad_phys, hipStream_t s) {
     if (!model_set) return fail(AWE_ESTATE, "awe_set_model has not been called on this plan");
     if (g.nrec > 0 && !resid) return fail(AWE_EINVAL, "resid is NULL but nrec > 0");
     const bool want_grad = grad_phys != nullptr;
     if (want_grad && !have_ckpt)
         return fail(AWE_ESTATE, "a gradient needs a preceding awe_forward with ckpt_every > 0");
     awe_status st;
-    if (!mu0 && ((st = alloc_field(&mu0)) || (st = alloc_field(&mu1)))) return st;
-    if (want_grad && !grad && (st = alloc_field(&grad))) return st;
+    if (!mu0 && ((st = alloc_field(&mu0, s)) || (st = alloc_field(&mu1, s)))) return st;
+    if (want_grad && !grad && (st = alloc_field(&grad, s))) return st;
     if (want_grad && rev_mode && rev.pos >= rev.sched.size())
         return fail(AWE_ESTATE, "the binomial checkpoints were used by an earlier gradient; run awe_forward_binomial again");
     if (want_grad && !img_tuned) {
@@ -1011,58 +1084,43 @@ awe_status Plan::adjoint(const float* resid, float* src_adj, float* grad_phys, h
     AWE_HIP(launch_fill(mu1, L.total, 0.f, s));
     if (want_grad) AWE_HIP(launch_fill(grad, L.total, 0.f, s));
     if (src_adj && g.nsrc > 0) AWE_HIP(launch_fill(src_adj + (size_t)(g.nt - 1) * g.nsrc, g.nsrc, 0.f, s));
-    float* m1 = mu0;   // mu[n+1]
-    float* m2 = mu1;   // mu[n+2]
-    const float inv_vol = (float)(1.0 / vol);
+    AdjJob& j = adj_job;
+    j = AdjJob{};
+    j.resid = resid;
+    j.src_adj = src_adj;
+    j.grad_phys = grad_phys;
+    j.m1 = mu0;   // mu[n+1]
+    j.m2 = mu1;   // mu[n+2]
+    j.mode = !want_grad ? AdjJob::kTranspose : rev_mode ? AdjJob::kBinomial : AdjJob::kPeriodic;
+    j.n = g.nt - 1;
+    if (want_grad) {
+        AWE_HIP(launch_fill(w0, L.total, 0.f, s));   // w0 serves as u[0] = u[-1] = 0
+        const int K = ckpt_K;
+        j.seg = j.mode == AdjJob::kPeriodic ? (g.nt + K - 1) / K - 1 : -1;
+        j.seg_ready = false;
+    }
+    j.active = true;
+    return AWE_OK;
+}
 
-    // mu[n] from (mu[n+1], mu[n+2]) in place over mu[n+2], then one launch
-    // that injects the residual row n into mu[n] and samples mu[n+1] (left
-    // untouched) at the sources into row n of the adjoint source.
-    auto adj_step = [&](int n, const float* usnap) -> awe_status {
-        const bool img = usnap != nullptr;
-        StepArgs a{m1, m2, m2, coef, d_ez, d_ey, d_ex, usnap, img ? grad : nullptr};
-        const LaunchShape& sh = img ? img_shape : fwd_shape;
-        AWE_HIP(timed(img ? 1 : 0, s, [&] { return launch_step(L, k, a, img ? kStepImaging : kStepPlain, sh.cfg, sh.zchunk, s); }));
-        InjectOp inj;
-        if (g.nrec > 0) {
-            inj.field = m2;
-            inj.coef = coef;
-            inj.node = rec_csr.node;
-            inj.rowptr = rec_csr.rowptr;
-            inj.pt = rec_csr.pt;
-            inj.w = rec_csr.w;
-            inj.values = resid + (size_t)n * g.nrec;
-            inj.usnap = usnap;
-            inj.grad = img ? grad : nullptr;
-            inj.nrows = rec_csr.nrows;
-        }
-        SampleOp smp;
-        if (src_adj && g.nsrc > 0 && n <= g.nt - 2) {
-            smp.out = src_adj + (size_t)n * g.nsrc;
-            smp.field = m1;
-            smp.node = src_node;
-            smp.w = src_w;
-            smp.scale = inv_vol;
-            smp.npts = g.nsrc;
-            smp.corners = corners;
-        }
-        AWE_HIP(timed(2, s, [&] { return launch_sparse(inj, smp, s); }));
-        std::swap(m1, m2);
-        return AWE_OK;
-    };
-
-    if (!want_grad) {
-        for (int n = g.nt - 1; n >= 0; --n)
-            if ((st = adj_step(n, nullptr))) return st;
+awe_status Plan::adjoint_advance(int max_steps, hipStream_t s, bool* done) {
+    AdjJob& j = adj_job;
+    *done = false;
+    if (!j.active) return fail(AWE_ESTATE, "no adjoint sweep in progress");
+    awe_status st;
+    float* const zero = w0;
+    const float* qsrc = g.nsrc ? wavelet_copy : nullptr;
+    int budget = max_steps;
+    if (j.mode == AdjJob::kTranspose) {
+        for (; j.n >= 0 && budget > 0; --j.n, --budget)
+            if ((st = adj_step(j.n, nullptr, s))) return st;
+        if (j.n >= 0) return AWE_OK;
         have_grad = false;
+        j.active = false;
+        *done = true;
         return AWE_OK;
     }
-
-    float* zero = w0;                         // u[0] = u[-1] = 0
-    AWE_HIP(launch_fill(zero, L.total, 0.f, s));
-    const float* qsrc = g.nsrc ? wavelet_copy : nullptr;
-
-    if (rev_mode) {
+    if (j.mode == AdjJob::kBinomial) {
         // The rest of the binomial schedule: recompute forward steps from
         // stored states and visit t = nt-1 .. 0 with the adjoint step.
         auto buf = [&](int b) { return b < 0 ? zero : rev_pool[b]; };
@@ -1071,50 +1129,70 @@ awe_status Plan::adjoint(const float* resid, float* src_adj, float* grad_phys, h
             [&](int n, int uc, int up, int out) {
                 return advance(buf(uc), buf(up), buf(out), qsrc ? qsrc + (size_t)n * g.nsrc : nullptr, nullptr, s);
             },
-            [&](int t, int uc) { return adj_step(t, t >= 1 ? buf(uc) : nullptr); });
+            [&](int t, int uc) { return adj_step(t, t >= 1 ? buf(uc) : nullptr, s); });
         if (st) return st;
-        AWE_HIP(launch_fold(grad_phys, grad, L, phys, g.nbl, (float)(-1.0 / (g.dt * g.dt)), d_fold_cells, n_fold_cells, s));
+        AWE_HIP(launch_fold(j.grad_phys, grad, L, phys, g.nbl, (float)(-1.0 / (g.dt * g.dt)), d_fold_cells, n_fold_cells, s));
         cur = prev = zero;   // the wavefield state no longer holds u[nt-1]
         have_ckpt = false;
         ++fwd_id;            // the stored states are consumed
         have_grad = true;
+        j.active = false;
+        *done = true;
         return AWE_OK;
     }
-
-    // Reverse sweep over segments [jK, min(jK+K, nt) - 1], j = S-1 .. 0.
+    // Reverse sweep over segments [jK, min(jK+K, nt) - 1], j = S-1 .. 0: the
+    // segment's states are recomputed into the slot buffers (stored states
+    // are used in place), then visited from the last to the first.
     const int K = ckpt_K;
-    const int S = (g.nt + K - 1) / K;
-    std::vector<const float*> ptr;            // ptr[t - (t0 - 1)] = u[t]
-    for (int j = S - 1; j >= 0; --j) {
-        const int t0 = j * K;
+    while (j.seg >= 0 && budget > 0) {
+        const int t0 = j.seg * K;
         const int t1 = std::min(t0 + K, g.nt) - 1;
-        ptr.assign(t1 - t0 + 2, nullptr);
-        auto at = [&](int t) -> const float*& { return ptr[t - (t0 - 1)]; };
-        for (int t = t0 - 1; t <= t1; ++t) {
-            if (t <= 0) at(t) = zero;
-            else {
-                auto it = stored.find(t);
-                at(t) = it != stored.end() ? it->second : nullptr;
+        auto at = [&](int t) -> const float*& { return j.ptr[t - (t0 - 1)]; };   // u[t]
+        if (!j.seg_ready) {
+            j.ptr.assign(t1 - t0 + 2, nullptr);
+            for (int t = t0 - 1; t <= t1; ++t) {
+                if (t <= 0) at(t) = zero;
+                else {
+                    auto it = stored.find(t);
+                    at(t) = it != stored.end() ? it->second : nullptr;
+                }
             }
+            j.slot = 0;
+            j.t = t0 + 1;
+            j.n = t1;
+            j.seg_ready = true;
         }
-        int slot = 0;
-        for (int t = t0 + 1; t <= t1; ++t) {
-            if (at(t)) continue;
-            float* dst = slots[slot++];
-            if ((st = advance(at(t - 1), at(t - 2), dst, qsrc ? qsrc + (size_t)(t - 1) * g.nsrc : nullptr, nullptr, s)))
+        for (; j.t <= t1 && budget > 0; ++j.t) {
+            if (at(j.t)) continue;
+            float* dst = slots[j.slot++];
+            if ((st = advance(at(j.t - 1), at(j.t - 2), dst, qsrc ? qsrc + (size_t)(j.t - 1) * g.nsrc : nullptr,
+                              nullptr, s)))
                 return st;
-            at(t) = dst;
+            at(j.t) = dst;
+            --budget;
         }
-        for (int n = t1; n >= t0; --n)
-            if ((st = adj_step(n, n >= 1 ? at(n) : nullptr))) return st;
+        if (j.t <= t1) break;
+        for (; j.n >= t0 && budget > 0; --j.n, --budget)
+            if ((st = adj_step(j.n, j.n >= 1 ? at(j.n) : nullptr, s))) return st;
+        if (j.n >= t0) break;
+        --j.seg;
+        j.seg_ready = false;
     }
+    if (j.seg >= 0) return AWE_OK;
     // g_phys = fold(-(1/dt^2) * accumulated imaging)
-    AWE_HIP(launch_fold(grad_phys, grad, L, phys, g.nbl, (float)(-1.0 / (g.dt * g.dt)), d_fold_cells, n_fold_cells, s));
+    AWE_HIP(launch_fold(j.grad_phys, grad, L, phys, g.nbl, (float)(-1.0 / (g.dt * g.dt)), d_fold_cells, n_fold_cells, s));
     // w0 served as the zero field: the wavefield state is now (0, 0), as after
     // a binomial gradient (the stored states stay valid for another gradient)
     cur = prev = zero;
     have_grad = true;
+    j.active = false;
+    *done = true;
     return AWE_OK;
 }
 
-
+awe_status Plan::adjoint(const float* resid, float* src_adj, float* grad_phys, hipStream_t s) {
+    awe_status st = adjoint_begin(resid, src_adj, grad_phys, s);
+    bool done = false;
+    while (!st && !done) st = adjoint_advance(1 << 30, s, &done);
+    return st;
+}

@@ -212,6 +212,30 @@ struct awe_plan_s {
     int rev_snaps = -1;             // snapshots of the schedule in rev (-1: none)
     bool rev_mode = false;          // the stored states are binomial (else periodic)
     bool have_ckpt = false, have_grad = false;
+    // Sweeps in progress (forward_begin / forward_advance, adjoint_begin /
+    // adjoint_advance): where a sweep cut into chunks resumes.
+    struct FwdJob {
+        const float* wavelet = nullptr;
+        float* traces = nullptr;
+        int K = 0;
+        int n = 0;              // next step: u[n+1] is produced next
+        bool active = false;
+    } fwd_job;
+    struct AdjJob {
+        enum Mode { kTranspose = 0, kBinomial = 1, kPeriodic = 2 };
+        int mode = kTranspose;
+        const float* resid = nullptr;
+        float* src_adj = nullptr;
+        float* grad_phys = nullptr;
+        float *m1 = nullptr, *m2 = nullptr;   // mu[n+1], mu[n+2]
+        int n = 0;              // next adjoint step
+        int seg = -1;           // periodic: segment being swept (S-1 .. 0)
+        bool seg_ready = false; // its state table is set up
+        int t = 0;              // next state to recompute in the segment
+        int slot = 0;           // next free slot buffer
+        std::vector<const float*> ptr;   // u[t] of the segment, t = t0-1 .. t1
+        bool active = false;
+    } adj_job;
     // Changes whenever the forward state a gradient reads (model, stored
     // states, wavelet copy) is replaced or consumed (awe_forward_id).
     int64_t fwd_id = 0;
@@ -239,10 +263,15 @@ struct awe_plan_s {
     awe_status forward_binomial(const float* wavelet, float* traces, int snapshots, hipStream_t s);
     awe_status step(int n0, int nsteps, const float* wavelet, float* traces, hipStream_t s);
     awe_status adjoint(const float* resid, float* src_adj, float* grad_phys, hipStream_t s);
+    awe_status forward_begin(const float* wavelet, float* traces, int K, hipStream_t s);
+    awe_status forward_advance(int max_steps, hipStream_t s, bool* done);
+    awe_status adjoint_begin(const float* resid, float* src_adj, float* grad_phys, hipStream_t s);
+    awe_status adjoint_advance(int max_steps, hipStream_t s, bool* done);
+    awe_status adj_step(int n, const float* usnap, hipStream_t s);
     awe_status born(const float* wavelet, const float* dm_phys, float* traces, hipStream_t s);
 
     awe_status alloc(void** p, size_t bytes);
-    awe_status alloc_field(float** p);
+    awe_status alloc_field(float** p, hipStream_t s);
     template <class T>
     awe_status upload(T** dst, const std::vector<T>& v);
     void release(void* p);
@@ -251,9 +280,9 @@ struct awe_plan_s {
     awe_status advance_tb(int n0, int nsteps, const float* wavelet, float* traces, int first_row, hipStream_t s);
     awe::InjectOp src_op(float* field, const float* q_row, float* t_acc) const;
     awe::SampleOp rec_op(float* row, const float* field) const;
-    awe_status ensure_gradient_storage(int K);
-    awe_status ensure_binomial_storage(int snapshots);
-    awe_status ensure_adjoint_storage();
+    awe_status ensure_gradient_storage(int K, hipStream_t s);
+    awe_status ensure_binomial_storage(int snapshots, hipStream_t s);
+    awe_status ensure_adjoint_storage(hipStream_t s);
     void release_periodic();
     void release_binomial();
     awe_status tune(bool img, hipStream_t user_stream);

@@ -51,6 +51,22 @@ sparse_k(InjectOp a, SampleOp b) {
     }
 }
 
+// The sum over shots of per-shot gradients (Eq. 2 sums the misfit over
+// shots, so its gradient is the sum of theirs), in a fixed order: element i
+// of out is sum_{p = 0..nparts-1} parts[p][i] accumulated in FP64 from
+// parts[0] up and rounded once, whatever order the parts were computed in.
+struct SumParts {
+    const float* p[kMaxSumParts];
+};
+__global__ void __launch_bounds__(kBlock)
+sum_parts_k(float* out, SumParts parts, int nparts, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        double acc = 0.0;
+        for (int q = 0; q < nparts; ++q) acc += (double)parts.p[q][i];
+        out[i] = (float)acc;
+    }
+}
+
 struct PadGeo {
     int64_t n0, n1, n2;          // padded extents
     int64_t p0, p1, p2;          // physical extents
@@ -317,6 +333,15 @@ hipError_t launch_misfit(const float* tr, const float* obs, int64_t n, float* re
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(sum_partials_k, dim3(1), dim3(kBlock), 0, s, partial, blocks, result);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_parts(float* out, const float* const* parts, int nparts, int64_t n, hipStream_t s) {
+    if (nparts < 1 || nparts > kMaxSumParts) return hipErrorInvalidValue;
+    if (n <= 0) return hipSuccess;
+    SumParts sp{};
+    for (int q = 0; q < nparts; ++q) sp.p[q] = parts[q];
+    hipLaunchKernelGGL(sum_parts_k, dim3(blocks_for(n, 16384)), dim3(kBlock), 0, s, out, sp, nparts, n);
     return hipGetLastError();
 }
 

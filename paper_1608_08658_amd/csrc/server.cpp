@@ -49,8 +49,14 @@ struct Request {
     int64_t id = 0;
     awe_geometry g{};
     std::vector<double> src, rec;
-    std::vector<float> m, wavelet;
+    std::vector<float> m, wavelet, obs;
     float* traces_host = nullptr;
+    // gradient requests: checkpoint interval, observed traces (obs, copied at
+    // submit) and where the gradient and the misfit go
+    bool gradient = false;
+    int K = 0;
+    float* grad_dev = nullptr;
+    double* phi_host = nullptr;
     uint64_t bytes = 0;
     int state = AWE_REQ_QUEUED;
     double t[4] = {-1, -1, -1, -1};
@@ -63,7 +69,10 @@ struct Request {
     float* d_m = nullptr;
     float* d_wav = nullptr;
     float* d_tr = nullptr;
-    int next = 0;             // next step index n (u[n+1] is produced next)
+    float* d_obs = nullptr;   // gradient: observed traces, then the residual in place
+    double* d_phi = nullptr;  // gradient: misfit
+    enum Phase { kForward = 0, kAdjoint = 1, kDone = 2 };
+    int phase = kForward;
 };
 
 // A stream with its two chunk events, reused by later requests.
@@ -75,7 +84,7 @@ struct Lane {
 // Device memory of a retired request, awaiting a batched free.
 struct Grave {
     awe_plan plan = nullptr;
-    float* bufs[3] = {nullptr, nullptr, nullptr};
+    void* bufs[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
 }  // namespace
@@ -117,7 +126,7 @@ void awe_server_s::free_graves() {
     }
     for (Grave& x : g) {
         if (x.plan) awe_plan_destroy(x.plan);
-        for (float* p : x.bufs)
+        for (void* p : x.bufs)
             if (p) (void)hipFree(p);
     }
     std::lock_guard<std::mutex> lk(mu);
@@ -141,18 +150,22 @@ void awe_server_s::finish(Request* r, int state, const std::string& err) {
     gr.bufs[0] = r->d_m;
     gr.bufs[1] = r->d_wav;
     gr.bufs[2] = r->d_tr;
+    gr.bufs[3] = r->d_obs;
+    gr.bufs[4] = r->d_phi;
     Lane ln;
     ln.stream = r->stream;
     ln.ev[0] = r->ev[0];
     ln.ev[1] = r->ev[1];
     r->plan = nullptr;
-    r->d_m = r->d_wav = r->d_tr = nullptr;
+    r->d_m = r->d_wav = r->d_tr = r->d_obs = nullptr;
+    r->d_phi = nullptr;
     r->stream = nullptr;
     r->ev[0] = r->ev[1] = nullptr;
     std::vector<float>().swap(r->m);
     std::vector<float>().swap(r->wavelet);
+    std::vector<float>().swap(r->obs);
     std::lock_guard<std::mutex> lk(mu);
-    if (gr.plan || gr.bufs[0] || gr.bufs[1] || gr.bufs[2]) {
+    if (gr.plan || gr.bufs[0] || gr.bufs[1] || gr.bufs[2] || gr.bufs[3] || gr.bufs[4]) {
         graves.push_back(gr);
         grave_bytes += r->bytes;
     }
@@ -208,16 +221,50 @@ bool awe_server_s::start(Request* r, std::string& err) {
     if (nw && !hip_ok(hipMemcpyAsync(r->d_wav, r->wavelet.data(), nw * sizeof(float), hipMemcpyHostToDevice,
                                      r->stream), "copy wavelet"))
         return false;
+    if (r->gradient) {
+        if (ntr && !hip_ok(hipMalloc(&r->d_obs, ntr * sizeof(float)), "hipMalloc")) return false;
+        if (!hip_ok(hipMalloc(&r->d_phi, sizeof(double)), "hipMalloc")) return false;
+        if (ntr && !hip_ok(hipMemcpyAsync(r->d_obs, r->obs.data(), ntr * sizeof(float), hipMemcpyHostToDevice,
+                                          r->stream), "copy d_obs"))
+            return false;
+    }
     st = awe_set_model(r->plan, r->d_m, r->stream);   // synchronises r->stream
     if (st) { err = awe_last_error(); return false; }
-    if (ntr && !hip_ok(awe::launch_fill(r->d_tr, r->g.nrec, 0.f, r->stream), "zero traces")) return false;
-    // zero initial state, as in awe_forward
-    if (!hip_ok(awe::launch_fill(r->plan->w0, r->plan->L.total, 0.f, r->stream), "zero state")) return false;
-    if (!hip_ok(awe::launch_fill(r->plan->w1, r->plan->L.total, 0.f, r->stream), "zero state")) return false;
-    r->plan->cur = r->plan->w0;
-    r->plan->prev = r->plan->w1;
-    r->next = 0;
+    // the forward of awe_forward, advanced a chunk at a time by the engine
+    st = r->plan->forward_begin(r->d_wav, r->d_tr, r->gradient ? r->K : 0, r->stream);
+    if (st) { err = awe_last_error(); return false; }
+    r->phase = Request::kForward;
     return true;
+}
+
+// Enqueues the request's next chunk: up to `chunk` forward steps, then (for a
+// gradient) the misfit and up to `chunk` steps of the adjoint sweep.  The
+// arithmetic is that of awe_forward, awe_misfit and awe_adjoint on a plan
+// run alone.
+static awe_status advance_request(Request* r, int chunk) {
+    bool done = false;
+    awe_status st;
+    if (r->phase == Request::kForward) {
+        if ((st = r->plan->forward_advance(chunk, r->stream, &done))) return st;
+        if (!done) return AWE_OK;
+        if (!r->gradient) {
+            r->phase = Request::kDone;
+            return AWE_OK;
+        }
+        // residual = traces - d_obs (in place over d_obs) and its misfit
+        const int64_t ntr = (int64_t)r->g.nt * r->g.nrec;
+        hipError_t e = awe::launch_misfit(r->d_tr, r->d_obs, ntr, r->d_obs, r->plan->d_mpart, awe::kReduceBlocks,
+                                          r->d_phi, r->stream);
+        if (e != hipSuccess) return fail(AWE_EHIP, "misfit: %s", hipGetErrorString(e));
+        if ((st = r->plan->adjoint_begin(r->d_obs, nullptr, r->grad_dev, r->stream))) return st;
+        r->phase = Request::kAdjoint;
+        return AWE_OK;
+    }
+    if (r->phase == Request::kAdjoint) {
+        if ((st = r->plan->adjoint_advance(chunk, r->stream, &done))) return st;
+        if (done) r->phase = Request::kDone;
+    }
+    return AWE_OK;
 }
 
 void awe_server_s::run() {
@@ -288,15 +335,12 @@ void awe_server_s::run() {
                 --r->inflight;
                 progressed = true;
             }
-            const int last = r->g.nt - 1;
-            while (!failed && r->inflight < 2 && r->next < last) {
-                const int n = std::min(chunk, last - r->next);
-                if (r->plan->step(r->next, n, r->d_wav, r->d_tr, r->stream)) {
+            while (!failed && r->inflight < 2 && r->phase != Request::kDone) {
+                if (advance_request(r, chunk)) {
                     err = awe_last_error();
                     failed = true;
                     break;
                 }
-                r->next += n;
                 const hipError_t e = hipEventRecord(r->ev[r->ev_head], r->stream);
                 if (e != hipSuccess) {
                     err = hipGetErrorString(e);
@@ -308,12 +352,14 @@ void awe_server_s::run() {
                 progressed = true;
             }
             bool done = false;
-            if (!failed && r->next >= last && r->inflight == 0) {
+            if (!failed && r->phase == Request::kDone && r->inflight == 0) {
                 // every step has completed, so the copy-out waits for nothing else
                 const size_t ntr = (size_t)r->g.nt * r->g.nrec;
                 hipError_t e = hipSuccess;
-                if (ntr) e = hipMemcpyAsync(r->traces_host, r->d_tr, ntr * sizeof(float), hipMemcpyDeviceToHost,
-                                            r->stream);
+                if (ntr && r->traces_host)
+                    e = hipMemcpyAsync(r->traces_host, r->d_tr, ntr * sizeof(float), hipMemcpyDeviceToHost, r->stream);
+                if (e == hipSuccess && r->gradient && r->phi_host)
+                    e = hipMemcpyAsync(r->phi_host, r->d_phi, sizeof(double), hipMemcpyDeviceToHost, r->stream);
                 if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
                 if (e != hipSuccess) {
                     err = hipGetErrorString(e);
@@ -362,26 +408,10 @@ awe_status awe_server_create(double hbm_fraction, int32_t chunk_steps, int32_t m
     return AWE_OK;
 }
 
-awe_status awe_server_submit(awe_server srv, const awe_geometry* g, const float* m, const float* wavelet,
-                             float* traces, int64_t* ticket) {
-    if (!srv || !ticket) return fail(AWE_EINVAL, "NULL argument");
-    awe_status st = awe::validate(g);
-    if (st) return st;
-    if (!m) return fail(AWE_EINVAL, "model is NULL");
-    if (g->nsrc > 0 && !wavelet) return fail(AWE_EINVAL, "wavelet is NULL");
-    if (g->nrec > 0 && !traces) return fail(AWE_EINVAL, "traces is NULL");
-    auto r = std::make_unique<Request>();
-    r->g = *g;
-    r->src.assign(g->src_coords, g->src_coords + (size_t)g->nsrc * g->ndim);
-    r->rec.assign(g->rec_coords, g->rec_coords + (size_t)g->nrec * g->ndim);
-    r->g.src_coords = r->src.data();
-    r->g.rec_coords = r->rec.data();
-    size_t nm = 1;
-    for (int a = 0; a < g->ndim; ++a) nm *= (size_t)g->shape[a];
-    r->m.assign(m, m + nm);
-    if (g->nsrc > 0) r->wavelet.assign(wavelet, wavelet + (size_t)g->nt * g->nsrc);
-    r->traces_host = traces;
-    r->bytes = awe::footprint_bytes(g, 0) + nm * 4 + r->wavelet.size() * 4 + (size_t)g->nt * g->nrec * 4;
+}  // extern "C"
+
+// Copies the request's inputs, sizes its footprint and queues it.
+static awe_status submit_request(awe_server srv, std::unique_ptr<Request> r, int64_t* ticket) {
     std::lock_guard<std::mutex> lk(srv->mu);
     if (srv->stop) return fail(AWE_EBUSY, "server is shutting down");
     if (r->bytes > srv->budget)
@@ -395,6 +425,69 @@ awe_status awe_server_submit(awe_server srv, const awe_geometry* g, const float*
     ++srv->n_submitted;
     srv->wake.notify_all();
     return AWE_OK;
+}
+
+static std::unique_ptr<Request> make_request(const awe_geometry* g, const float* m, const float* wavelet,
+                                             float* traces) {
+    auto r = std::make_unique<Request>();
+    r->g = *g;
+    r->src.assign(g->src_coords, g->src_coords + (size_t)g->nsrc * g->ndim);
+    r->rec.assign(g->rec_coords, g->rec_coords + (size_t)g->nrec * g->ndim);
+    r->g.src_coords = r->src.data();
+    r->g.rec_coords = r->rec.data();
+    size_t nm = 1;
+    for (int a = 0; a < g->ndim; ++a) nm *= (size_t)g->shape[a];
+    r->m.assign(m, m + nm);
+    if (g->nsrc > 0) r->wavelet.assign(wavelet, wavelet + (size_t)g->nt * g->nsrc);
+    r->traces_host = traces;
+    // plan + model + wavelet + traces on the device
+    r->bytes = awe::footprint_bytes(g, 0) + nm * 4 + r->wavelet.size() * 4 + (size_t)g->nt * g->nrec * 4;
+    return r;
+}
+
+extern "C" {
+
+awe_status awe_server_submit(awe_server srv, const awe_geometry* g, const float* m, const float* wavelet,
+                             float* traces, int64_t* ticket) {
+    if (!srv || !ticket) return fail(AWE_EINVAL, "NULL argument");
+    awe_status st = awe::validate(g);
+    if (st) return st;
+    if (!m) return fail(AWE_EINVAL, "model is NULL");
+    if (g->nsrc > 0 && !wavelet) return fail(AWE_EINVAL, "wavelet is NULL");
+    if (g->nrec > 0 && !traces) return fail(AWE_EINVAL, "traces is NULL");
+    try {
+        return submit_request(srv, make_request(g, m, wavelet, traces), ticket);
+    } catch (const std::bad_alloc&) {
+        return fail(AWE_ENOMEM, "host allocation failed");
+    }
+}
+
+awe_status awe_server_submit_gradient(awe_server srv, const awe_geometry* g, const float* m, const float* wavelet,
+                                      const float* d_obs, int32_t ckpt_every, float* traces, float* grad_dev,
+                                      double* phi, int64_t* ticket) {
+    if (!srv || !ticket) return fail(AWE_EINVAL, "NULL argument");
+    awe_status st = awe::validate(g);
+    if (st) return st;
+    if (!m) return fail(AWE_EINVAL, "model is NULL");
+    if (g->nsrc > 0 && !wavelet) return fail(AWE_EINVAL, "wavelet is NULL");
+    if (g->nrec > 0 && !d_obs) return fail(AWE_EINVAL, "d_obs is NULL");
+    if (!grad_dev) return fail(AWE_EINVAL, "grad_dev is NULL");
+    if (ckpt_every < 1) return fail(AWE_EINVAL, "ckpt_every must be >= 1");
+    try {
+        std::unique_ptr<Request> r = make_request(g, m, wavelet, traces);
+        const size_t ntr = (size_t)g->nt * g->nrec;
+        r->obs.assign(d_obs, d_obs + ntr);
+        r->gradient = true;
+        r->K = ckpt_every;
+        r->grad_dev = grad_dev;
+        r->phi_host = phi;
+        // + checkpoints, segment slots and adjoint fields, the observed traces
+        // (the residual overwrites them) and the misfit
+        r->bytes += awe::footprint_bytes(g, ckpt_every) - awe::footprint_bytes(g, 0) + ntr * 4 + sizeof(double);
+        return submit_request(srv, std::move(r), ticket);
+    } catch (const std::bad_alloc&) {
+        return fail(AWE_ENOMEM, "host allocation failed");
+    }
 }
 
 awe_status awe_server_poll(awe_server srv, int64_t ticket, int32_t* state, double* times) {

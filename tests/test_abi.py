@@ -97,3 +97,20 @@ def test_null_arguments_are_errors_not_crashes():
     assert L.awe_plan_destroy(None) == _lib.AWE_OK
     assert L.awe_server_destroy(None) == _lib.AWE_OK
     assert L.awe_misfit(None, None, 0, None, None, None) == _lib.AWE_EINVAL
+
+
+def test_null_arguments_of_the_newer_calls():
+    import ctypes as C
+    L = _lib.lib()
+    i64 = C.c_int64()
+    out = (C.c_double * 6)()
+    assert L.awe_forward_id(None, C.byref(i64)) == _lib.AWE_EINVAL
+    assert L.awe_adjoint_checked(None, 0, None, None, None, None) == _lib.AWE_EINVAL
+    assert L.awe_plan_time_kernels(None, 1) == _lib.AWE_EINVAL
+    assert L.awe_plan_kernel_times(None, out) == _lib.AWE_EINVAL
+    assert L.awe_server_submit_gradient(None, None, None, None, None, 5, None, None, None, None) == _lib.AWE_EINVAL
+    parts = (C.c_void_p * 1)(None)
+    assert L.awe_sum_fields(None, parts, 1, 4, None) == _lib.AWE_EINVAL          # no output
+    assert L.awe_sum_fields(C.c_void_p(16), parts, 1, 4, None) == _lib.AWE_EINVAL   # a NULL part
+    assert L.awe_sum_fields(C.c_void_p(16), parts, 0, 4, None) == _lib.AWE_EINVAL   # no parts
+    assert L.awe_sum_fields(C.c_void_p(16), parts, 65, 4, None) == _lib.AWE_EINVAL  # too many parts

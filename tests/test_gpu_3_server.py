@@ -144,3 +144,137 @@ def test_degenerate_requests_complete():
         if shot.nt == 1 or len(shot.src_coords) == 0:
             assert np.all(tr == 0.0), shot.name
     srv.close()
+
+
+def _gradient_shot(seed, kind, order, nt):
+    """A small shot, its true model (5% smooth perturbation) and d_obs from the
+    oracle on the true model."""
+    import oracle
+    from helpers import oracle_problem, small_2d_shot, small_3d_shot
+    shot = small_2d_shot(seed, order, nt=nt) if kind == "2d" else small_3d_shot(seed, order, nt=nt)
+    dt = float(shot_dt(shot))
+    rng = np.random.default_rng(seed)
+    m_true = shot.m * (1.0 + 0.05 * synth.random_state(rng, shot.shape, 2.0))
+    w = shot.wavelet(dt).astype(np.float32)
+    d_obs = oracle.Operator(oracle_problem(shot, dt), m_true).forward(w)["traces"].astype(np.float32)
+    return shot, dt, w, d_obs
+
+
+def _gradient_alone(shot, dt, w, d_obs, K):
+    """The same gradient through direct plan calls (forward, misfit, adjoint)."""
+    import paper_1608_08658_amd as awe
+    plan = gpu_plan(shot, dt)
+    plan.set_model(dev(shot.m))
+    tr = plan.forward(dev(w), ckpt_every=K)
+    phi, resid = awe.misfit(tr, dev(d_obs))
+    _, g = plan.adjoint(resid, want_src_adj=False, want_grad=True)
+    out = host(g), host(tr), phi
+    plan.close()
+    return out
+
+
+def test_gradient_requests_alone_in_the_mix_and_against_the_oracle():
+    # Gradient requests among forward requests: each gradient, its traces and
+    # misfit equal direct plan calls bit for bit (the server cuts the same
+    # sweeps into chunks), every forward equals its shot alone, and the
+    # gradient matches the oracle's.
+    import torch
+    import oracle
+    import paper_1608_08658_amd as awe
+    from helpers import oracle_problem, rel_l2
+    K = 7
+    # long enough that the direct wave reaches the receivers (a misfit of
+    # numerical precursors alone would make the comparison meaningless)
+    grads = [_gradient_shot(1301, "3d", 8, 60), _gradient_shot(1302, "2d", 4, 450), _gradient_shot(1303, "3d", 16, 60)]
+    fwds = _requests(45, 5, scale=0.1)
+    srv = awe.Server(hbm_fraction=0.5, chunk_steps=16, max_active=4)
+    sub = []
+    for i in range(max(len(grads), len(fwds))):
+        if i < len(grads):
+            shot, dt, w, d_obs = grads[i]
+            g = torch.full(shot.shape, float("nan"), dtype=torch.float32, device="cuda")
+            t, tr, phi = srv.submit_gradient(_geom(shot, dt), shot.m, w, d_obs, K, g)
+            sub.append(("grad", i, t, tr, phi, g))
+        if i < len(fwds):
+            shot, dt, w = fwds[i]
+            t, tr = srv.submit(_geom(shot, dt), shot.m, w)
+            sub.append(("fwd", i, t, tr, None, None))
+    for entry in sub:
+        srv.wait(entry[2], timeout=300)
+    stats = srv.stats()
+    log(f"server stats {stats}")
+    assert stats["completed"] == len(sub) and stats["failed"] == 0
+    for kind, i, t, tr, phi, g in sub:
+        if kind == "fwd":
+            shot, dt, w = fwds[i]
+            assert np.array_equal(tr.astype(np.float64), _alone(shot, dt, w)), shot.name
+            continue
+        shot, dt, w, d_obs = grads[i]
+        g_alone, tr_alone, phi_alone = _gradient_alone(shot, dt, w, d_obs, K)
+        g_srv = host(g)
+        ref = oracle.Operator(oracle_problem(shot, dt), shot.m).gradient(w, d_obs)
+        e = rel_l2(g_srv, ref["grad"])
+        log(f"  gradient request {shot.name}: bitwise {np.array_equal(g_srv, g_alone)}, phi {phi[0]!r} vs "
+            f"{phi_alone!r} (oracle {ref['phi']:.6e}), oracle gradient rel {e:.2e}")
+        assert np.array_equal(g_srv, g_alone), shot.name
+        assert np.array_equal(tr.astype(np.float64), tr_alone), shot.name
+        assert phi[0] == phi_alone
+        assert e <= 1e-4
+    srv.close()
+
+
+def test_served_gradients_summed_over_shots_against_the_oracle():
+    # Three shots on one model (sources at different points): the server's
+    # per-shot gradients summed in shot order on the device (FP64, one
+    # rounding) equal that sum formed on the host, and the oracle's summed
+    # gradient to 1e-4.
+    import torch
+    import oracle
+    import paper_1608_08658_amd as awe
+    from helpers import oracle_problem, rel_l2
+    shot0, dt, w, _ = _gradient_shot(1401, "3d", 8, 60)
+    rng = np.random.default_rng(1401)
+    m_true = shot0.m * (1.0 + 0.05 * synth.random_state(rng, shot0.shape, 2.0))
+    span = np.array([(n - 1) * h for n, h in zip(shot0.shape, shot0.spacing)])
+    K = 9
+    srv = awe.Server(hbm_fraction=0.5, chunk_steps=10, max_active=2)
+    grads, tickets, ref_sum = [], [], None
+    for k, frac in enumerate(([0.2, 0.3, 0.4], [0.25, 0.7, 0.6], [0.3, 0.5, 0.15])):
+        import copy
+        shot = copy.copy(shot0)
+        shot.src_coords = np.array([np.array(frac) * span])
+        op_true = oracle.Operator(oracle_problem(shot, dt), m_true)
+        d_obs = op_true.forward(w)["traces"].astype(np.float32)
+        ref = oracle.Operator(oracle_problem(shot, dt), shot.m).gradient(w, d_obs)["grad"]
+        ref_sum = ref if ref_sum is None else ref_sum + ref
+        g = torch.empty(shot.shape, dtype=torch.float32, device="cuda")
+        tickets.append(srv.submit_gradient(_geom(shot, dt), shot.m, w, d_obs, K, g, want_traces=False)[0])
+        grads.append(g)
+    for t in tickets:
+        srv.wait(t, timeout=300)
+    srv.close()
+    total = host(awe.sum_fields(grads))
+    on_host = sum(host(g) for g in grads).astype(np.float32).astype(np.float64)
+    e = rel_l2(total, ref_sum)
+    log(f"  sum of 3 shots: oracle rel {e:.2e}, equal to the host FP64 sum {np.array_equal(total, on_host)}")
+    assert np.array_equal(total, on_host)
+    assert e <= 1e-4
+
+
+def test_gradient_request_arguments_and_budget(monkeypatch):
+    import torch
+    import paper_1608_08658_amd as awe
+    shot, dt, w, d_obs = _gradient_shot(1501, "3d", 8, 30)
+    g = torch.empty(shot.shape, dtype=torch.float32, device="cuda")
+    srv = awe.Server(hbm_fraction=0.5, chunk_steps=8, max_active=2)
+    with pytest.raises(awe.AweError) as e:
+        srv.submit_gradient(_geom(shot, dt), shot.m, w, d_obs, 0, g)
+    assert e.value.status == -1
+    srv.close()
+    fp = awe.footprint(_geom(shot, dt), 5)
+    monkeypatch.setenv("AWE_SERVER_BUDGET_BYTES", str(fp))     # below footprint + inputs
+    srv = awe.Server(hbm_fraction=1.0, chunk_steps=8, max_active=2)
+    with pytest.raises(awe.AweError) as e:
+        srv.submit_gradient(_geom(shot, dt), shot.m, w, d_obs, 5, g)
+    assert e.value.status == -2
+    srv.close()

@@ -1,4 +1,4 @@
-"""Pins of the oracle's FD weights and Laplacian (Sec. IV.A.1)."""
+"""Pins of the oracle's FD weights and Laplacian (Sec. IV.A, derivative expressions)."""
 import math
 import os
 from fractions import Fraction
