@@ -300,6 +300,19 @@ awe_status awe_misfit(const float* traces_dev, const float* d_obs_dev, int64_t n
                       float* resid_dev, double* phi_host, awe_stream stream);
 
 /*
+ * awe_misfit for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops): the same kernels and the same FP64
+ * sum in the same order, so *phi_dev equals awe_misfit's *phi_host bit for
+ * bit.  It allocates nothing: the per-block partial sums live in a fixed
+ * 8 KiB device array of the library (one per device, kept until the process
+ * ends), enough for any n.  Φ is written to phi_dev (device, one double) and
+ * nothing is synchronised.  Calls that overlap on one device (different
+ * streams or threads) share that array and race; serialise them.
+ */
+awe_status awe_misfit_noalloc(const float* traces_dev, const float* d_obs_dev, int64_t n,
+                              float* resid_dev, double* phi_dev, awe_stream stream);
+
+/*
  * Sum over shots: out_dev[i] = sum_{p=0}^{nparts-1} parts_host[p][i] for
  * i < n, accumulated in FP64 in the order p = 0, 1, ... and rounded once to
  * FP32.  The misfit of Eq. 2 over several shots is the sum of theirs, so its

@@ -60,6 +60,7 @@ _SIGNATURES = {
     "awe_step": (_I32, [_P, _I32, _I32, _P, _P, _P]),
     "awe_get_state": (_I32, [_P, _P, _P, _P]),
     "awe_misfit": (_I32, [_P, _P, _I64, _P, C.POINTER(_D), _P]),
+    "awe_misfit_noalloc": (_I32, [_P, _P, _I64, _P, _P, _P]),
     "awe_server_create": (_I32, [_D, _I32, _I32, C.POINTER(_P)]),
     "awe_server_submit": (_I32, [_P, C.POINTER(Geometry), _P, _P, _P, C.POINTER(_I64)]),
     "awe_server_submit_gradient": (_I32, [_P, C.POINTER(Geometry), _P, _P, _P, _I32, _P, _P, C.POINTER(_D),

@@ -22,7 +22,7 @@ BUILD_DIR = os.path.join(HERE, "_build")
 
 SOURCES = ["kernels_stencil_hi.hip", "kernels_stencil_lo.hip", "kernels_stencil.hip", "kernels_stencil2d_tb.hip",
            "kernels_aux.hip",
-           "engine.cpp", "checkpoint.cpp", "api.cpp", "server.cpp"]
+           "noalloc.hip", "engine.cpp", "checkpoint.cpp", "api.cpp", "server.cpp"]
 
 ARCH = "gfx950"
 FLAGS = [
