@@ -259,7 +259,7 @@ def bench_serve(awe, synth, count=200, scale=0.5, seed=4, max_active=16, chunk=6
             "requests": count, "saturation": sat, "poisson": points}
 
 
-def bench_served_gradient(torch, awe, synth, n=300, nt=1500, nshots=32, max_active=2):
+def bench_served_gradient(torch, awe, synth, n=300, nt=1500, nshots=32, max_active=1):
     """Served gradient requests: per-shot FWI gradients submitted to the shot
     server (awe_server_submit_gradient: forward with checkpoints, misfit and
     adjoint-state gradient, advanced in chunks), summed on the device in

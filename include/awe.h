@@ -329,15 +329,15 @@ awe_status awe_sum_fields(float* out_dev, const float* const* parts_host, int32_
  * Requests (forward shots, or gradients) carry their own geometry, model
  * and wavelet (host memory, copied at submit).  An engine thread admits
  * queued requests in arrival order while the sum of their awe_footprint
- * stays within hbm_fraction of the
- * device memory that was free at creation and at most max_active run at
- * once.  Each running request advances on its own stream in chunks of
- * chunk_steps time steps, two chunks in flight, independently of the others
- * (no batch-wide barrier); a request that finishes is retired and its traces
- * copied to traces_host (host [nt][nrec], kept by the server until the
- * request is done).  While requests run the engine waits for no stream but
- * the one it is working on: plans are set up on their request's stream
- * without launch timing, and device memory of retired requests stays
+ * stays within hbm_fraction of the device memory that was free at creation
+ * and at most max_active run at once.  Each running request advances on its
+ * own stream in chunks of chunk_steps time steps, two chunks in flight,
+ * independently of the others (no batch-wide barrier); a request that
+ * finishes is retired and its traces copied to traces_host (host
+ * [nt][nrec], kept by the server until the request is done).  While
+ * requests run the engine waits for no stream but the one it is working on:
+ * plans are set up on their request's stream (launch shapes are timed only
+ * while no other request runs), and device memory of retired requests stays
  * allocated (counted against the budget) until nothing runs or the queue
  * head needs the room, then is freed in one batch.  Stats' "bytes
  * reserved" counts running requests plus retired ones not yet freed;

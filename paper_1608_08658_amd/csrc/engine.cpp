@@ -564,7 +564,7 @@ bool nearby_shape(const TuneKey& key, LaunchShape& out) {
 // 128^2..2040^2.
 LaunchShape awe::default_shape(const Layout& L) {
     if (L.ndim != 3) return LaunchShape{0, 4};
-    return L.points() < 27000000 ? LaunchShape{1, 8} : LaunchShape{1, 28};
+    return LaunchShape{1, balanced_zchunk(L.n[0], L.points() < 27000000 ? 8 : 28)};
 }
 
 awe_status Plan::tune(bool img, hipStream_t user_stream) {
@@ -588,6 +588,7 @@ awe_status Plan::tune(bool img, hipStream_t user_stream) {
         }
         LaunchShape near{};
         if (g.ndim == 3 && nearby_shape(key, near)) {
+            near.zchunk = balanced_zchunk(L.n[0], near.zchunk);   // the same chunk count, even here
             shape = near;
             g_tune_cache[key] = near;
             return AWE_OK;
@@ -599,9 +600,16 @@ awe_status Plan::tune(bool img, hipStream_t user_stream) {
         // chunks shorter than 28 planes only for the plain step: timed alone
         // they can win the imaging step too, but in the adjoint sweep (which
         // alternates with recomputed forward steps) they were ~3% slower
-        for (int cfg : {0, 1, 3, 4, 5})
-            for (int zc : {8, 14, 21, 28, 42, 56, 70, 84})
-                if (!img || zc >= 28) cand.push_back({cfg, zc});
+        // chunks balanced over the z extent (same count, equal lengths)
+        for (int cfg : {0, 1, 3, 4, 5}) {
+            int last = -1;
+            for (int zc : {8, 14, 21, 28, 42, 56, 70, 84}) {
+                const int bz = balanced_zchunk(L.n[0], zc);
+                if ((img && zc < 28) || bz == last) continue;
+                cand.push_back({cfg, bz});
+                last = bz;
+            }
+        }
     } else {
         for (int zc : {4, 8, 16, 32, 64}) cand.push_back({0, zc});
         for (int zc : {8, 16, 32, 64}) cand.push_back({1, zc});

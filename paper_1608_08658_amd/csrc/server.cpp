@@ -14,8 +14,9 @@
 // interleaved in time with other requests.
 //
 // The engine never waits for the whole device while requests run: a plan is
-// set up on its request's stream (no launch timing: the autotuner takes a
-// cached or nearby shape, else the built-in one), traces are copied out only
+// set up on its request's stream (launch shapes are timed only while no other
+// request runs; otherwise the autotuner takes a cached or nearby shape, else
+// the built-in one), traces are copied out only
 // once the request's last chunk has completed, and streams and events are
 // reused.  hipFree waits for every stream on the device, so a retired
 // request's device memory is kept (counted against the budget) and freed in
@@ -111,7 +112,7 @@ struct awe_server_s {
     std::thread engine;
 
     void run();
-    bool start(Request* r, std::string& err);
+    bool start(Request* r, bool idle, std::string& err);
     void finish(Request* r, int state, const std::string& err);
     void free_graves();
     void release_lanes();
@@ -182,7 +183,10 @@ void awe_server_s::finish(Request* r, int state, const std::string& err) {
     changed.notify_all();
 }
 
-bool awe_server_s::start(Request* r, std::string& err) {
+// idle: nothing else runs on the device, so the plan may time its launch
+// shapes (timings among other requests' kernels would be distorted and
+// would stall them).
+bool awe_server_s::start(Request* r, bool idle, std::string& err) {
     auto hip_ok = [&](hipError_t e, const char* what) {
         if (e == hipSuccess) return true;
         err = std::string(what) + ": " + hipGetErrorString(e);
@@ -205,7 +209,7 @@ bool awe_server_s::start(Request* r, std::string& err) {
     awe_status st = AWE_OK;
     try {
         r->plan = new awe_plan_s();
-        st = r->plan->init(&r->g, r->stream, false);
+        st = r->plan->init(&r->g, r->stream, idle);
     } catch (const std::bad_alloc&) {
         st = fail(AWE_ENOMEM, "host allocation failed");
     } catch (...) {
@@ -241,7 +245,7 @@ bool awe_server_s::start(Request* r, std::string& err) {
 // gradient) the misfit and up to `chunk` steps of the adjoint sweep.  The
 // arithmetic is that of awe_forward, awe_misfit and awe_adjoint on a plan
 // run alone.
-static awe_status advance_request(Request* r, int chunk) {
+static awe_status advance_request(Request* r, int chunk, bool alone) {
     bool done = false;
     awe_status st;
     if (r->phase == Request::kForward) {
@@ -256,6 +260,7 @@ static awe_status advance_request(Request* r, int chunk) {
         hipError_t e = awe::launch_misfit(r->d_tr, r->d_obs, ntr, r->d_obs, r->plan->d_mpart, awe::kReduceBlocks,
                                           r->d_phi, r->stream);
         if (e != hipSuccess) return fail(AWE_EHIP, "misfit: %s", hipGetErrorString(e));
+        r->plan->timed_tune = alone;   // the imaging step's shape is timed only with the device to itself
         if ((st = r->plan->adjoint_begin(r->d_obs, nullptr, r->grad_dev, r->stream))) return st;
         r->phase = Request::kAdjoint;
         return AWE_OK;
@@ -304,7 +309,12 @@ void awe_server_s::run() {
         }
         for (Request* r : admitted) {
             std::string err;
-            if (start(r, err)) {
+            bool idle;
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                idle = active.empty();
+            }
+            if (start(r, idle, err)) {
                 std::lock_guard<std::mutex> lk(mu);
                 r->t[2] = now_s(t0);
                 active.push_back(r);
@@ -336,7 +346,7 @@ void awe_server_s::run() {
                 progressed = true;
             }
             while (!failed && r->inflight < 2 && r->phase != Request::kDone) {
-                if (advance_request(r, chunk)) {
+                if (advance_request(r, chunk, running.size() == 1)) {
                     err = awe_last_error();
                     failed = true;
                     break;

@@ -30,4 +30,14 @@ int pick_timed_shape(size_t n, const float* t, ZchunkOf zchunk_of, float tie = 0
     return best;
 }
 
+// The z-chunk of the same chunk count as `zc` over nz planes with the chunks
+// as equal as possible: ceil(nz / ceil(nz / zc)).  A grid of 150 planes cut
+// into 28-plane chunks ends with a 10-plane chunk that pays the same warm-up
+// as a full one; 25-plane chunks cut it evenly into the same six.
+inline int balanced_zchunk(long long nz, int zc) {
+    if (nz < 1 || zc < 1) return zc < 1 ? 1 : zc;
+    const long long chunks = (nz + zc - 1) / zc;
+    return (int)((nz + chunks - 1) / chunks);
+}
+
 }  // namespace awe

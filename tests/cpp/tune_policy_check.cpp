@@ -66,6 +66,21 @@ int main() {
         }
         if (fails) break;
     }
+    // balanced z-chunks: the chunk count of zc, lengths differing by at most one
+    CHECK(awe::balanced_zchunk(150, 28) == 25);
+    CHECK(awe::balanced_zchunk(480, 56) == 54);
+    CHECK(awe::balanced_zchunk(480, 84) == 80);
+    CHECK(awe::balanced_zchunk(9, 8) == 5);
+    CHECK(awe::balanced_zchunk(8, 8) == 8);
+    CHECK(awe::balanced_zchunk(3, 8) == 3);
+    for (long long nz = 1; nz <= 700; ++nz)
+        for (int zc : chunks) {
+            const int b = awe::balanced_zchunk(nz, zc);
+            const long long n0 = (nz + zc - 1) / zc, n1 = (nz + b - 1) / b;
+            CHECK(b >= 1 && b <= zc && n1 == n0);
+            CHECK(nz - (n1 - 1) * b >= b - n1);        // the last chunk is short by less than the count
+            if (fails) break;
+        }
     if (fails) return 1;
     std::printf("ok\n");
     return 0;
