@@ -39,6 +39,8 @@ def log(msg):
 
 
 PROFILE = os.path.join(ROOT, "profiles", "step3d_o8_336cube_forward.md")
+PROFILE_O16_STEP = os.path.join(ROOT, "profiles", "step3d_o16_480cube_forward.md")
+PROFILE_O16_IMAGING = os.path.join(ROOT, "profiles", "step3d_o16_480cube_gradient_imaging.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_1608_08658_amd", "csrc", "stencil_impl.hpp")
 
 
@@ -53,13 +55,13 @@ def kernel_source_digest(path=KERNEL_SRC):
     return hashlib.sha256("\n".join(line for line in lines if line.strip()).encode()).hexdigest()
 
 
-def profiled_traffic(shape):
-    """HBM bytes per stencil launch from the committed rocprofv3 counter
+def profiled_traffic(shape, path=PROFILE):
+    """HBM bytes per stencil launch from a committed rocprofv3 counter
     summary, or None when the kernel code or launch shape has changed since
     the counters were taken."""
     try:
         facts = {}
-        for line in open(PROFILE):
+        for line in open(path):
             if ":" in line and line.startswith("    ") and not line.strip().startswith(("cd ", "|")):
                 k, v = line.strip().split(":", 1)
                 facts[k.strip()] = v.split()[0] if v.split() else ""
@@ -155,6 +157,12 @@ def bench_gradient(torch, awe, synth, n=400, nt=2000, snapshots=20):
                              "achieved_GBps": gbs, "frac": gbs / HBM_PEAK_GBS}
     if kt["points"][0]:
         kernels["points"] = {"launches_timed": kt["points"][0], "avg_launch_us": kt["points"][1]}
+    info = plan.info()
+    for kind, shape, path in (("step", info["forward_shape"], PROFILE_O16_STEP),
+                              ("imaging", info["imaging_shape"], PROFILE_O16_IMAGING)):
+        if kind in kernels:
+            kernels[kind]["launch_shape"] = list(shape)
+            kernels[kind]["traffic"] = profiled_traffic(tuple(shape), path)
     log("gradient kernels: " + ", ".join(f"{k} {v['avg_launch_us']:.1f} us" +
                                           (f" ({100 * v['frac']:.1f}% of peak)" if "frac" in v else "")
                                           for k, v in kernels.items()))

@@ -600,10 +600,12 @@ awe_status Plan::tune(bool img, hipStream_t user_stream) {
         // chunks shorter than 28 planes only for the plain step: timed alone
         // they can win the imaging step too, but in the adjoint sweep (which
         // alternates with recomputed forward steps) they were ~3% slower
-        // chunks balanced over the z extent (same count, equal lengths)
-        for (int cfg : {0, 1, 3, 4, 5}) {
+        // chunks balanced over the z extent (same count, equal lengths); long
+        // chunks (a few per column) pay off on deep high-order grids: 64x32
+        // tiles with two 240-plane chunks are the fastest 480^3 order-16 step
+        for (int cfg : {0, 1, 2, 3, 4, 5}) {
             int last = -1;
-            for (int zc : {8, 14, 21, 28, 42, 56, 70, 84}) {
+            for (int zc : {8, 14, 21, 28, 42, 56, 70, 84, 96, 120, 160, 240}) {
                 const int bz = balanced_zchunk(L.n[0], zc);
                 if ((img && zc < 28) || bz == last) continue;
                 cand.push_back({cfg, bz});

@@ -27,8 +27,9 @@
 //   * the current plane, with an M-wide x/y halo, is staged in LDS (double
 //     buffered, one barrier per plane) for the x and y derivatives; the halo
 //     cells are re-read from L2 / the Infinity Cache;
-//   * the loads for plane z+1 are issued before the barrier of plane z so their
-//     latency hides behind the arithmetic of plane z;
+//   * the loads for plane z+1 (z+2 in plain steps of orders 10-16) are issued
+//     before the barrier of plane z so their latency hides behind the
+//     arithmetic of the planes in between;
 //   * each thread owns RY consecutive y rows, so y-neighbours inside its own
 //     rows come from registers;
 //   * a wavefront owns 64 columns of one thread row, so row indices and row
@@ -253,68 +254,87 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk, FusedSparse fs) {
     for (int r = 0; r < RY; ++r) eyv[r] = (y0 + r < g.ny) ? a.eta_y[y0 + r] : 0.f;
 
 
-    // register queue of the z-neighbourhood: q[r][j] = uc(z - M + j)
-    float q[RY][NQ];
+    // Loads run PF planes ahead of the plane computed: one plane for low
+    // orders, two for plain steps of orders 10-16, where one plane of
+    // arithmetic does not cover the load latency (the order-14 and order-16
+    // steps wait on memory for ~40% of a wave's life with one plane).
+    constexpr int PF = (M >= 5 && MODE == kStepPlain) ? 2 : 1;
+    // register queue of the z-neighbourhood: logical slot j holds uc(z - M + j),
+    // j = 0..2M, in NQ2 >= 2M+1 physical slots; NQ2 is a multiple of PF so that
+    // the loop unrolled NQ2 times also cycles the PF prefetch register sets
+    // at compile time
+    constexpr int NQ2 = (NQ % PF) ? NQ + PF - NQ % PF : NQ;
+    float q[RY][NQ2];
 #pragma unroll
     for (int j = 1; j < NQ; ++j)
 #pragma unroll
         for (int r = 0; r < RY; ++r) q[r][j] = bload(r_uc, v_ld, soff(z0 - M + j - 1) + s_row[r]);
     drain_vmem();
 
-    float fr[RY], pv[RY], cv[RY], sv[RY], gv[RY], hxv[RY], hyv[NH], ezn;
-    auto fetch = [&](int z) {
+    // what fetch(z) loads for plane z: the queue head uc(z + M), u_prev, C
+    // (and snapshot and gradient), the x and y halo of uc(z), eta_z
+    struct Pre {
+        float fr[RY], pv[RY], cv[RY], sv[RY], gv[RY], hxv[RY], hyv[NH], ezn;
+    };
+    Pre pre[PF];
+    auto fetch = [&](Pre& P, int z) {
         // first in the batch: vector-memory counters retire in order, so the
-        // compute of plane z - 1 only waits for loads issued before this one
-        ezn = a.eta_z[z];
+        // compute of earlier planes only waits for loads issued before this one
+        P.ezn = a.eta_z[z];
         const uint32_t so = soff(z), sf = soff(z + M);
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-            fr[r] = bload(r_uc, v_ld, sf + s_row[r]);
+            P.fr[r] = bload(r_uc, v_ld, sf + s_row[r]);
             // arrays read only at owned points: lanes past the grid read
             // nothing (a clamped column can sit in a line of its own)
-            pv[r] = bload<AWE_CPOL_STREAM>(r_up, v_st, so + s_row[r]);
-            cv[r] = bload<AWE_CPOL_STREAM>(r_cf, v_st, so + s_row[r]);
+            P.pv[r] = bload<AWE_CPOL_STREAM>(r_up, v_st, so + s_row[r]);
+            P.cv[r] = bload<AWE_CPOL_STREAM>(r_cf, v_st, so + s_row[r]);
             if (MODE == kStepImaging || MODE == kStepBorn) {
-                sv[r] = bload<AWE_CPOL_STREAM>(r_us, v_st, so + s_row[r]);
-                gv[r] = bload<AWE_CPOL_STREAM>(r_gr, v_st, so + s_row[r]);
+                P.sv[r] = bload<AWE_CPOL_STREAM>(r_us, v_st, so + s_row[r]);
+                P.gv[r] = bload<AWE_CPOL_STREAM>(r_gr, v_st, so + s_row[r]);
             }
-            hxv[r] = bload(r_uc, v_hx, so + s_row[r]);
+            P.hxv[r] = bload(r_uc, v_hx, so + s_row[r]);
         }
 #pragma unroll
         for (int i = 0; i < NH; ++i)
-            if (kHyFull || ty + i * BY < 2 * M) hyv[i] = bload(r_uc, v_ld, so + s_hy[i]);
+            if (kHyFull || ty + i * BY < 2 * M) P.hyv[i] = bload(r_uc, v_ld, so + s_hy[i]);
     };
-    fetch(z0);
+#pragma unroll
+    for (int i = 0; i < PF; ++i)
+        if (z0 + i < z1) fetch(pre[i], z0 + i);
 
     // One plane.  The z-queue is never shifted: in iteration z the logical
-    // slot j (plane z - M + j) lives in physical slot (j + PH) % NQ, with PH
-    // advancing by one per plane.  The loop is unrolled NQ times so PH is a
-    // compile-time constant and no register moves are needed.
-    auto one_plane = [&](auto ph, int z) {
+    // slot j (plane z - M + j) lives in physical slot (j + PH) % NQ2, with PH
+    // advancing by one per plane, and plane z0 + i uses prefetch set i % PF.
+    // The loop is unrolled NQ2 times so PH and the set are compile-time
+    // constants and no register moves are needed.
+    auto one_plane = [&](auto ph, auto set, int z) {
         constexpr int PH = decltype(ph)::value;
-        auto Q = [&](int r, int j) -> float& { return q[r][(j + PH) % NQ]; };
+        Pre& P = pre[decltype(set)::value];
+        auto Q = [&](int r, int j) -> float& { return q[r][(j + PH) % NQ2]; };
         const int b = (z - z0) & 1;
 #pragma unroll
-        for (int r = 0; r < RY; ++r) Q(r, NQ - 1) = fr[r];
+        for (int r = 0; r < RY; ++r) Q(r, NQ - 1) = P.fr[r];
         // stage plane z in LDS
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             lds[b][M + ty * RY + r][M + lxb + tx] = Q(r, M);
-            if (hl || hr) lds[b][M + ty * RY + r][hlx] = hxv[r];
+            if (hl || hr) lds[b][M + ty * RY + r][hlx] = P.hxv[r];
         }
 #pragma unroll
         for (int i = 0; i < NH; ++i)
-            if (kHyFull || ty + i * BY < 2 * M) lds[b][hyrow[i]][M + lxb + tx] = hyv[i];
+            if (kHyFull || ty + i * BY < 2 * M) lds[b][hyrow[i]][M + lxb + tx] = P.hyv[i];
 
         float p[RY], c[RY], s[RY], gg[RY];
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-            p[r] = pv[r];
-            c[r] = cv[r];
-            if (MODE == kStepImaging || MODE == kStepBorn) { s[r] = sv[r]; gg[r] = gv[r]; }
+            p[r] = P.pv[r];
+            c[r] = P.cv[r];
+            if (MODE == kStepImaging || MODE == kStepBorn) { s[r] = P.sv[r]; gg[r] = P.gv[r]; }
         }
-        const float ezv = ezn;
-        if (z + 1 < z1) fetch(z + 1);
+        const float ezv = P.ezn;
+        // the set is consumed: refill it with plane z + PF
+        if (z + PF < z1) fetch(P, z + PF);
         lds_barrier();
 
         const uint32_t so = soff(z);
@@ -354,12 +374,13 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk, FusedSparse fs) {
         }
     };
     // before plane z0 the queue holds planes z0-M .. z0+M-1 in physical slots
-    // 1..NQ-1, i.e. logical slot j sits in (j + 1) % NQ: the first plane has PH = 1
+    // 1..NQ-1, i.e. logical slot j sits in (j + 1) % NQ2: the first plane has PH = 1
     int z = z0;
     for (;;) {
-        static_for<NQ>([&](auto s_) {
-            constexpr int PH = (decltype(s_)::value + 1) % NQ;
-            if (z < z1) one_plane(std::integral_constant<int, PH>{}, z);
+        static_for<NQ2>([&](auto s_) {
+            constexpr int PH = (decltype(s_)::value + 1) % NQ2;
+            if (z < z1)
+                one_plane(std::integral_constant<int, PH>{}, std::integral_constant<int, decltype(s_)::value % PF>{}, z);
             ++z;
         });
         if (z >= z1) break;
