@@ -337,11 +337,12 @@ awe_status awe_sum_fields(float* out_dev, const float* const* parts_host, int32_
  * [nt][nrec], kept by the server until the request is done).  While
  * requests run the engine waits for no stream but the one it is working on:
  * plans are set up on their request's stream (launch shapes are timed only
- * while no other request runs), and device memory of retired requests stays
- * allocated (counted against the budget) until nothing runs or the queue
- * head needs the room, then is freed in one batch.  Stats' "bytes
- * reserved" counts running requests plus retired ones not yet freed;
- * "iterations" counts passes of the engine loop.
+ * while no other request runs), and device memory of retired requests goes
+ * to a pool (counted against the budget) from which later requests take
+ * buffers of the same size, freed in one batch only when the server has no
+ * work left or the queue head needs the room.  Stats' "bytes reserved"
+ * counts running requests plus pooled memory; "iterations" counts passes of
+ * the engine loop.
  * ------------------------------------------------------------------------- */
 enum { AWE_REQ_QUEUED = 0, AWE_REQ_RUNNING = 1, AWE_REQ_DONE = 2, AWE_REQ_FAILED = 3 };
 

@@ -302,9 +302,35 @@ using Plan = awe_plan_s;
 // ---------------------------------------------------------------------------
 // device memory helpers
 // ---------------------------------------------------------------------------
+void* BufferPool::take(size_t n) {
+    auto it = free_list.find(n);
+    if (it == free_list.end()) return nullptr;
+    void* p = it->second;
+    free_list.erase(it);
+    bytes -= n;
+    return p;
+}
+
+void BufferPool::give(void* p, size_t n) {
+    if (!p) return;
+    free_list.emplace(n, p);
+    bytes += n;
+}
+
+void BufferPool::release_all() {
+    for (auto& kv : free_list) (void)hipFree(kv.second);
+    free_list.clear();
+    bytes = 0;
+}
+
 awe_status Plan::alloc(void** p, size_t bytes) {
     *p = nullptr;
     if (bytes == 0) return AWE_OK;
+    if (pool && (*p = pool->take(bytes))) {
+        owned.push_back({*p, bytes});
+        held += bytes;
+        return AWE_OK;
+    }
     hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -341,12 +367,16 @@ void Plan::release(void* p) {
     auto it = std::find_if(owned.begin(), owned.end(), [p](const std::pair<void*, size_t>& o) { return o.first == p; });
     if (it == owned.end()) return;   // not the plan's
     held -= it->second;
+    if (pool) pool->give(p, it->second);
+    else (void)hipFree(p);
     owned.erase(it);
-    (void)hipFree(p);
 }
 
 Plan::~awe_plan_s() {
-    for (auto& o : owned) (void)hipFree(o.first);
+    for (auto& o : owned) {
+        if (pool) pool->give(o.first, o.second);
+        else (void)hipFree(o.first);
+    }
     timer_reset();
     for (auto& pr : timer_free) {
         (void)hipEventDestroy(pr.first);

@@ -35,6 +35,19 @@ struct LaunchShape {
 };
 LaunchShape default_shape(const Layout& L);
 
+// Device buffers kept for reuse by their owner (the shot server): a
+// retired plan's buffers come here instead of going to hipFree, and a new
+// plan takes one of the same size instead of calling hipMalloc.  The owner
+// hands buffers back only once the work that used them has completed.  Not
+// thread-safe: one thread owns it.
+struct BufferPool {
+    std::multimap<size_t, void*> free_list;
+    uint64_t bytes = 0;                  // bytes held in the free list
+    void* take(size_t n);                // a pooled buffer of exactly n bytes, or nullptr
+    void give(void* p, size_t n);
+    void release_all();                  // hipFree every pooled buffer (waits for the device)
+};
+
 struct DeviceCsr {
     int64_t* node = nullptr;
     int32_t* rowptr = nullptr;
@@ -172,6 +185,7 @@ struct awe_plan_s {
 
     // device buffers owned by the plan
     std::vector<std::pair<void*, size_t>> owned;   // allocation and its size
+    awe::BufferPool* pool = nullptr;   // if set: buffers come from and go back to it
     size_t held = 0;
     float* coef = nullptr;
     float *d_ez = nullptr, *d_ey = nullptr, *d_ex = nullptr;

@@ -19,8 +19,10 @@
 // the built-in one), traces are copied out only
 // once the request's last chunk has completed, and streams and events are
 // reused.  hipFree waits for every stream on the device, so a retired
-// request's device memory is kept (counted against the budget) and freed in
-// one batch when nothing runs or when the queue head needs the room.
+// request's device memory goes to a pool (counted against the budget) that
+// the next plans take their buffers from (same-sized fields of a repeated
+// grid need no new allocation), and the pool is freed in one batch only
+// when the server has no work or the queue head needs the room.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -82,12 +84,6 @@ struct Lane {
     hipEvent_t ev[2] = {nullptr, nullptr};
 };
 
-// Device memory of a retired request, awaiting a batched free.
-struct Grave {
-    awe_plan plan = nullptr;
-    void* bufs[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-};
-
 }  // namespace
 
 struct awe_server_s {
@@ -106,32 +102,43 @@ struct awe_server_s {
     std::vector<Request*> active;
     std::map<int64_t, std::unique_ptr<Request>> all;
     std::vector<Lane> lanes;     // idle streams
-    std::vector<Grave> graves;   // retired requests' device memory
-    uint64_t grave_bytes = 0;
+    // retired requests' device memory, reused by later plans (engine thread
+    // only; pool_bytes mirrors pool.bytes under mu for the stats)
+    awe::BufferPool pool;
+    uint64_t pool_bytes = 0;
     bool stop = false;
     std::thread engine;
 
     void run();
     bool start(Request* r, bool idle, std::string& err);
     void finish(Request* r, int state, const std::string& err);
-    void free_graves();
+    void free_pool();
     void release_lanes();
+    template <class T>
+    bool pool_alloc(T** p, size_t n, std::string& err);
+    void sync_pool_bytes();
 };
 
-void awe_server_s::free_graves() {
-    // engine thread (or after it has ended); the first hipFree waits for the device
-    std::vector<Grave> g;
-    {
-        std::lock_guard<std::mutex> lk(mu);
-        g.swap(graves);
-    }
-    for (Grave& x : g) {
-        if (x.plan) awe_plan_destroy(x.plan);
-        for (void* p : x.bufs)
-            if (p) (void)hipFree(p);
-    }
+void awe_server_s::sync_pool_bytes() {
     std::lock_guard<std::mutex> lk(mu);
-    if (graves.empty()) grave_bytes = 0;
+    pool_bytes = pool.bytes;
+}
+
+void awe_server_s::free_pool() {
+    // engine thread (or after it has ended); the first hipFree waits for the device
+    pool.release_all();
+    sync_pool_bytes();
+}
+
+// A request buffer: a pooled one of the same size if there is one.
+template <class T>
+bool awe_server_s::pool_alloc(T** p, size_t n, std::string& err) {
+    if ((*p = static_cast<T*>(pool.take(n)))) return true;
+    const hipError_t e = hipMalloc(p, n);
+    if (e == hipSuccess) return true;
+    (void)hipGetLastError();
+    err = std::string("hipMalloc: ") + hipGetErrorString(e);
+    return false;
 }
 
 void awe_server_s::release_lanes() {
@@ -144,15 +151,17 @@ void awe_server_s::release_lanes() {
 }
 
 void awe_server_s::finish(Request* r, int state, const std::string& err) {
-    // caller does not hold mu; waits for r's own stream only
+    // engine thread, caller does not hold mu; waits for r's own stream only:
+    // once it is idle nothing uses the request's buffers, and the plan and
+    // the buffers go back to the pool without freeing anything
     if (r->stream) (void)hipStreamSynchronize(r->stream);
-    Grave gr;
-    gr.plan = r->plan;
-    gr.bufs[0] = r->d_m;
-    gr.bufs[1] = r->d_wav;
-    gr.bufs[2] = r->d_tr;
-    gr.bufs[3] = r->d_obs;
-    gr.bufs[4] = r->d_phi;
+    delete r->plan;
+    const size_t nm = r->m.size(), nw = r->wavelet.size(), ntr = (size_t)r->g.nt * r->g.nrec;
+    pool.give(r->d_m, nm * sizeof(float));
+    pool.give(r->d_wav, nw * sizeof(float));
+    pool.give(r->d_tr, ntr * sizeof(float));
+    pool.give(r->d_obs, ntr * sizeof(float));
+    pool.give(r->d_phi, sizeof(double));
     Lane ln;
     ln.stream = r->stream;
     ln.ev[0] = r->ev[0];
@@ -166,10 +175,7 @@ void awe_server_s::finish(Request* r, int state, const std::string& err) {
     std::vector<float>().swap(r->wavelet);
     std::vector<float>().swap(r->obs);
     std::lock_guard<std::mutex> lk(mu);
-    if (gr.plan || gr.bufs[0] || gr.bufs[1] || gr.bufs[2] || gr.bufs[3] || gr.bufs[4]) {
-        graves.push_back(gr);
-        grave_bytes += r->bytes;
-    }
+    pool_bytes = pool.bytes;
     if (ln.stream) lanes.push_back(ln);
     else
         for (hipEvent_t e : ln.ev)
@@ -209,6 +215,7 @@ bool awe_server_s::start(Request* r, bool idle, std::string& err) {
     awe_status st = AWE_OK;
     try {
         r->plan = new awe_plan_s();
+        r->plan->pool = &pool;   // buffers of earlier requests of the same grid are reused
         st = r->plan->init(&r->g, r->stream, idle);
     } catch (const std::bad_alloc&) {
         st = fail(AWE_ENOMEM, "host allocation failed");
@@ -217,17 +224,17 @@ bool awe_server_s::start(Request* r, bool idle, std::string& err) {
     }
     if (st) { err = awe_last_error(); return false; }
     const size_t nm = r->m.size(), nw = r->wavelet.size(), ntr = (size_t)r->g.nt * r->g.nrec;
-    if (!hip_ok(hipMalloc(&r->d_m, nm * sizeof(float)), "hipMalloc")) return false;
-    if (nw && !hip_ok(hipMalloc(&r->d_wav, nw * sizeof(float)), "hipMalloc")) return false;
-    if (ntr && !hip_ok(hipMalloc(&r->d_tr, ntr * sizeof(float)), "hipMalloc")) return false;
+    if (!pool_alloc(&r->d_m, nm * sizeof(float), err)) return false;
+    if (nw && !pool_alloc(&r->d_wav, nw * sizeof(float), err)) return false;
+    if (ntr && !pool_alloc(&r->d_tr, ntr * sizeof(float), err)) return false;
     if (!hip_ok(hipMemcpyAsync(r->d_m, r->m.data(), nm * sizeof(float), hipMemcpyHostToDevice, r->stream), "copy m"))
         return false;
     if (nw && !hip_ok(hipMemcpyAsync(r->d_wav, r->wavelet.data(), nw * sizeof(float), hipMemcpyHostToDevice,
                                      r->stream), "copy wavelet"))
         return false;
     if (r->gradient) {
-        if (ntr && !hip_ok(hipMalloc(&r->d_obs, ntr * sizeof(float)), "hipMalloc")) return false;
-        if (!hip_ok(hipMalloc(&r->d_phi, sizeof(double)), "hipMalloc")) return false;
+        if (ntr && !pool_alloc(&r->d_obs, ntr * sizeof(float), err)) return false;
+        if (!pool_alloc(&r->d_phi, sizeof(double), err)) return false;
         if (ntr && !hip_ok(hipMemcpyAsync(r->d_obs, r->obs.data(), ntr * sizeof(float), hipMemcpyHostToDevice,
                                           r->stream), "copy d_obs"))
             return false;
@@ -279,15 +286,16 @@ void awe_server_s::run() {
         bool flush = false;
         {
             std::unique_lock<std::mutex> lk(mu);
-            if (!active.empty() || graves.empty()) {   // else free the retired memory first
+            // with no work left the pooled memory is freed first (below)
+            if (!active.empty() || !queue.empty() || pool_bytes == 0) {
                 wake.wait(lk, [&] { return stop || !queue.empty() || !active.empty(); });
-                if (stop && active.empty() && graves.empty()) break;
+                if (stop && active.empty() && pool_bytes == 0) break;
             }
             // FIFO admission (server_policy.hpp)
             awe::AdmitState as;
             as.budget = budget;
             as.reserved = reserved;
-            as.retired = grave_bytes;
+            as.retired = pool_bytes;
             as.running = (int)active.size();
             as.max_active = max_active;
             const awe::AdmitResult ar =
@@ -304,7 +312,7 @@ void awe_server_s::run() {
             }
         }
         if (flush) {
-            free_graves();
+            free_pool();
             continue;
         }
         for (Request* r : admitted) {
@@ -535,7 +543,7 @@ awe_status awe_server_stats(awe_server srv, int64_t* out) {
     out[3] = srv->n_failed;
     out[4] = (int64_t)srv->active.size();
     out[5] = (int64_t)srv->queue.size();
-    out[6] = (int64_t)(srv->reserved + srv->grave_bytes);
+    out[6] = (int64_t)(srv->reserved + srv->pool_bytes);
     out[7] = srv->iterations;
     return AWE_OK;
 }
@@ -555,7 +563,7 @@ awe_status awe_server_destroy(awe_server srv) {
         srv->changed.notify_all();
     }
     if (srv->engine.joinable()) srv->engine.join();
-    srv->free_graves();
+    srv->free_pool();
     srv->release_lanes();
     delete srv;
     return AWE_OK;

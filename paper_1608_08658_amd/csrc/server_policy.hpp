@@ -4,10 +4,11 @@
 // Requests wait in arrival order.  The head is admitted while fewer than
 // max_active requests run and its footprint fits the device-memory budget;
 // a request behind the head never overtakes it.  Device memory of retired
-// requests that has not been freed yet ("retired bytes") counts against the
-// budget: freeing it waits for every stream on the device, so it is freed
-// only when nothing runs (no one is stalled) or when the head would fit
-// once it is freed.
+// requests is kept in a pool for the next requests to reuse ("retired
+// bytes", counted against the budget): freeing it waits for every stream on
+// the device, so it is freed only when the server has no work at all
+// (nothing runs and nothing waits) or when the head would fit once it is
+// freed.
 #pragma once
 
 #include <cstdint>
@@ -31,7 +32,7 @@ struct AdmitResult {
 template <class BytesOf>
 AdmitResult admit_fifo(const AdmitState& s, int queued, BytesOf bytes_of) {
     AdmitResult r;
-    if (s.running == 0 && s.retired > 0) {   // nothing runs: freeing stalls no one
+    if (s.running == 0 && queued == 0 && s.retired > 0) {   // no work at all: freeing stalls no one
         r.free_retired = true;
         return r;
     }

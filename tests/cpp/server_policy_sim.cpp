@@ -4,8 +4,8 @@
 // leave their memory "retired" until the policy frees it.  Checked at every
 // decision: the budget holds for running plus retired bytes, at most
 // max_active run, admission is first-in first-out, memory is freed only when
-// nothing runs or when that lets the head in (and then the head is admitted),
-// and every request completes.  Prints "ok" and the counts, or the failed
+// the server has no work (nothing runs, nothing waits) or when that lets the
+// head in (and then the head is admitted), and every request completes.  Prints "ok" and the counts, or the failed
 // check, and exits non-zero on failure.
 #include <algorithm>
 #include <cstdint>
@@ -60,7 +60,7 @@ static bool simulate(int seed, int max_active, uint64_t budget, int n, long& fre
         CHECK(!(a.free_retired && a.count > 0));
         if (a.free_retired) {
             CHECK(retired > 0);
-            const bool idle = running.empty();
+            const bool idle = running.empty() && queue.empty();
             const bool head_fits_after = !queue.empty() && (int)running.size() < max_active &&
                                          reserved + bytes_of(0) <= budget && reserved + retired + bytes_of(0) > budget;
             CHECK(idle || head_fits_after);

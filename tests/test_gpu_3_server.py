@@ -278,3 +278,30 @@ def test_gradient_request_arguments_and_budget(monkeypatch):
         srv.submit_gradient(_geom(shot, dt), shot.m, w, d_obs, 5, g)
     assert e.value.status == -2
     srv.close()
+
+
+def test_repeated_gradient_requests_reuse_pooled_buffers_bit_for_bit():
+    # One request at a time: every later request of the same grid takes the
+    # earlier ones' retired buffers from the server's pool (its checkpoint
+    # fields among them) and must give the same bits as the first and as
+    # direct plan calls; with no work left the pool is freed.
+    import torch
+    import time
+    import paper_1608_08658_amd as awe
+    shot, dt, w, d_obs = _gradient_shot(1601, "3d", 8, 60)
+    K = 6
+    g_alone, tr_alone, phi_alone = _gradient_alone(shot, dt, w, d_obs, K)
+    srv = awe.Server(hbm_fraction=0.5, chunk_steps=9, max_active=1)
+    grads = [torch.full(shot.shape, float("nan"), dtype=torch.float32, device="cuda") for _ in range(3)]
+    subs = [srv.submit_gradient(_geom(shot, dt), shot.m, w, d_obs, K, g) for g in grads]
+    for t, _, _ in subs:
+        srv.wait(t, timeout=300)
+    for (t, tr, phi), g in zip(subs, grads):
+        assert np.array_equal(host(g), g_alone)
+        assert np.array_equal(tr.astype(np.float64), tr_alone)
+        assert phi[0] == phi_alone
+    t0 = time.time()
+    while srv.stats()["bytes_reserved"] and time.time() - t0 < 30:
+        time.sleep(0.01)
+    assert srv.stats()["bytes_reserved"] == 0
+    srv.close()
