@@ -432,12 +432,24 @@ def bench_paper_example(torch, awe, synth):
     t = ev[0].elapsed_time(ev[1]) / 1e3
     npad = int(np.prod(plan.padded))
     finite = bool(torch.isfinite(tr).all().item())
+    # the step kernel's own time (HIP events around every 4th launch, on an extra run)
+    plan.time_kernels(4)
+    plan.forward(w)
+    torch.cuda.synchronize()
+    n_timed, step_us = plan.kernel_times()["step"]
+    plan.time_kernels(0)
+    shape = plan.info()["forward_shape"]
     plan.close()
-    log(f"paper example: {shot.nt} samples in {t * 1e3:.1f} ms, {npad * (shot.nt - 1) / t / 1e9:.1f} Gpt/s")
+    log(f"paper example: {shot.nt} samples in {t * 1e3:.1f} ms, {npad * (shot.nt - 1) / t / 1e9:.1f} Gpt/s; "
+        f"step kernel {step_us:.1f} us in shape {shape}")
     return {"workload": "the paper's 3-D run: 201x201x70 + 40-point layer (150x281x281 computed), h = 15 m, "
                         "order 14, 10 Hz Ricker, 1 s modelled, synthetic layered model (the paper gives none)",
             "nt": shot.nt, "dt": dt, "forward_s": t, "grid_pt_updates_per_s": npad * (shot.nt - 1) / t,
-            "algorithmic_GBps": 16.0 * npad * (shot.nt - 1) / t / 1e9, "finite": finite}
+            "algorithmic_GBps": 16.0 * npad * (shot.nt - 1) / t / 1e9,
+            "step_kernel": {"avg_launch_us": step_us, "launches_timed": n_timed,
+                            "frac": 16.0 * npad / (step_us * 1e-6) / 8e12,
+                            "launch_shape": {"workgroup_cfg": shape[0], "zchunk": shape[1]}},
+            "finite": finite}
 
 
 def main():

@@ -330,7 +330,10 @@ awe_status awe_sum_fields(float* out_dev, const float* const* parts_host, int32_
  * and wavelet (host memory, copied at submit).  An engine thread admits
  * queued requests in arrival order while the sum of their awe_footprint
  * stays within hbm_fraction of the device memory that was free at creation
- * and at most max_active run at once.  Each running request advances on its
+ * and at most max_active run at once; while max_active run, one more request
+ * may be admitted and set up ahead (plan and uploads, on a host thread of
+ * its own), to start as soon as a slot frees (its state is already
+ * AWE_REQ_RUNNING, its footprint counted).  Each running request advances on its
  * own stream in chunks of chunk_steps time steps, two chunks in flight,
  * independently of the others (no batch-wide barrier); a request that
  * finishes is retired and its traces copied to traces_host (host

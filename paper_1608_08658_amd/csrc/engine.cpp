@@ -303,6 +303,7 @@ using Plan = awe_plan_s;
 // device memory helpers
 // ---------------------------------------------------------------------------
 void* BufferPool::take(size_t n) {
+    std::lock_guard<std::mutex> lk(mu);
     auto it = free_list.find(n);
     if (it == free_list.end()) return nullptr;
     void* p = it->second;
@@ -313,14 +314,21 @@ void* BufferPool::take(size_t n) {
 
 void BufferPool::give(void* p, size_t n) {
     if (!p) return;
+    std::lock_guard<std::mutex> lk(mu);
     free_list.emplace(n, p);
     bytes += n;
 }
 
 void BufferPool::release_all() {
+    std::lock_guard<std::mutex> lk(mu);
     for (auto& kv : free_list) (void)hipFree(kv.second);
     free_list.clear();
     bytes = 0;
+}
+
+uint64_t BufferPool::held() {
+    std::lock_guard<std::mutex> lk(mu);
+    return bytes;
 }
 
 awe_status Plan::alloc(void** p, size_t bytes) {
@@ -632,10 +640,12 @@ awe_status Plan::tune(bool img, hipStream_t user_stream) {
         // alternates with recomputed forward steps) they were ~3% slower
         // chunks balanced over the z extent (same count, equal lengths); long
         // chunks (a few per column) pay off on deep high-order grids: 64x32
-        // tiles with two 240-plane chunks are the fastest 480^3 order-16 step
+        // tiles with two 240-plane chunks are the fastest 480^3 order-16 step;
+        // 35 gives five chunks on 150-plane grids (30 planes each, the
+        // fastest order-14 step on the 150 x 281 x 281 grid)
         for (int cfg : {0, 1, 2, 3, 4, 5}) {
             int last = -1;
-            for (int zc : {8, 14, 21, 28, 42, 56, 70, 84, 96, 120, 160, 240}) {
+            for (int zc : {8, 14, 21, 28, 35, 42, 56, 70, 84, 96, 120, 160, 240}) {
                 const int bz = balanced_zchunk(L.n[0], zc);
                 if ((img && zc < 28) || bz == last) continue;
                 cand.push_back({cfg, bz});

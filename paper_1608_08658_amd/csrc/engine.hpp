@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <map>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -41,11 +42,13 @@ LaunchShape default_shape(const Layout& L);
 // hands buffers back only once the work that used them has completed.  Not
 // thread-safe: one thread owns it.
 struct BufferPool {
+    std::mutex mu;                       // plans on several host threads share one pool
     std::multimap<size_t, void*> free_list;
-    uint64_t bytes = 0;                  // bytes held in the free list
+    uint64_t bytes = 0;                  // bytes held in the free list (under mu)
     void* take(size_t n);                // a pooled buffer of exactly n bytes, or nullptr
     void give(void* p, size_t n);
     void release_all();                  // hipFree every pooled buffer (waits for the device)
+    uint64_t held();
 };
 
 struct DeviceCsr {

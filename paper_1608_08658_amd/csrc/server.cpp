@@ -18,7 +18,11 @@
 // request runs; otherwise the autotuner takes a cached or nearby shape, else
 // the built-in one), traces are copied out only
 // once the request's last chunk has completed, and streams and events are
-// reused.  hipFree waits for every stream on the device, so a retired
+// reused.  While max_active requests run, the next admitted request is set up
+// ahead on a host thread of its own (plan, uploads of the model, wavelet and
+// observed traces): it starts computing as soon as a running request
+// finishes, whose traces are then copied out while the device already works
+// on the next one.  hipFree waits for every stream on the device, so a retired
 // request's device memory goes to a pool (counted against the budget) that
 // the next plans take their buffers from (same-sized fields of a repeated
 // grid need no new allocation), and the pool is freed in one batch only
@@ -26,6 +30,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -76,6 +81,11 @@ struct Request {
     double* d_phi = nullptr;  // gradient: misfit
     enum Phase { kForward = 0, kAdjoint = 1, kDone = 2 };
     int phase = kForward;
+    // set up ahead (see above): the host thread doing it, its outcome
+    std::thread setup;
+    std::atomic<bool> ready{false};
+    bool setup_ok = false;
+    std::string setup_err;
 };
 
 // A stream with its two chunk events, reused by later requests.
@@ -108,8 +118,14 @@ struct awe_server_s {
     uint64_t pool_bytes = 0;
     bool stop = false;
     std::thread engine;
+    // engine thread: the request being set up ahead, or set up and waiting
+    // for a running slot (at most one)
+    Request* staged = nullptr;
 
     void run();
+    void stage(Request* r);
+    bool promote();
+    bool pump(Request* r, std::string& err, bool alone);
     bool start(Request* r, bool idle, std::string& err);
     void finish(Request* r, int state, const std::string& err);
     void free_pool();
@@ -120,8 +136,9 @@ struct awe_server_s {
 };
 
 void awe_server_s::sync_pool_bytes() {
+    const uint64_t b = pool.held();
     std::lock_guard<std::mutex> lk(mu);
-    pool_bytes = pool.bytes;
+    pool_bytes = b;
 }
 
 void awe_server_s::free_pool() {
@@ -174,8 +191,9 @@ void awe_server_s::finish(Request* r, int state, const std::string& err) {
     std::vector<float>().swap(r->m);
     std::vector<float>().swap(r->wavelet);
     std::vector<float>().swap(r->obs);
+    const uint64_t held = pool.held();
     std::lock_guard<std::mutex> lk(mu);
-    pool_bytes = pool.bytes;
+    pool_bytes = held;
     if (ln.stream) lanes.push_back(ln);
     else
         for (hipEvent_t e : ln.ev)
@@ -279,6 +297,59 @@ static awe_status advance_request(Request* r, int chunk, bool alone) {
     return AWE_OK;
 }
 
+// Sets r up on a host thread of its own while the running requests compute.
+void awe_server_s::stage(Request* r) {
+    staged = r;
+    r->ready.store(false);
+    r->setup = std::thread([this, r] {
+        (void)hipSetDevice(device);
+        std::string err;
+        const bool ok = start(r, false, err);
+        r->setup_ok = ok;
+        r->setup_err = err;
+        r->ready.store(true, std::memory_order_release);
+    });
+}
+
+// Moves the staged request, once set up, into a free running slot.  Returns
+// true if a request started running.
+bool awe_server_s::promote() {
+    Request* r = staged;
+    if (!r || !r->ready.load(std::memory_order_acquire)) return false;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        if ((int)active.size() >= max_active) return false;
+    }
+    r->setup.join();
+    staged = nullptr;
+    if (!r->setup_ok) {
+        finish(r, AWE_REQ_FAILED, r->setup_err);
+        return false;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    r->t[2] = now_s(t0);
+    active.push_back(r);
+    return true;
+}
+
+// Keeps two chunks of r in flight.  Returns false (err set) on failure.
+bool awe_server_s::pump(Request* r, std::string& err, bool alone) {
+    while (r->inflight < 2 && r->phase != Request::kDone) {
+        if (advance_request(r, chunk, alone)) {
+            err = awe_last_error();
+            return false;
+        }
+        const hipError_t e = hipEventRecord(r->ev[r->ev_head], r->stream);
+        if (e != hipSuccess) {
+            err = hipGetErrorString(e);
+            return false;
+        }
+        r->ev_head = (r->ev_head + 1) % 2;
+        ++r->inflight;
+    }
+    return true;
+}
+
 void awe_server_s::run() {
     (void)hipSetDevice(device);
     for (;;) {
@@ -287,19 +358,22 @@ void awe_server_s::run() {
         {
             std::unique_lock<std::mutex> lk(mu);
             // with no work left the pooled memory is freed first (below)
-            if (!active.empty() || !queue.empty() || pool_bytes == 0) {
-                wake.wait(lk, [&] { return stop || !queue.empty() || !active.empty(); });
-                if (stop && active.empty() && pool_bytes == 0) break;
+            if (!active.empty() || !queue.empty() || staged || pool_bytes == 0) {
+                wake.wait(lk, [&] { return stop || !queue.empty() || !active.empty() || staged; });
+                if (stop && active.empty() && !staged && pool_bytes == 0) break;
             }
-            // FIFO admission (server_policy.hpp)
+            // FIFO admission (server_policy.hpp) for max_active running
+            // requests plus one set up ahead; nothing is admitted past a
+            // request set up ahead, which would otherwise start after a
+            // younger one
             awe::AdmitState as;
             as.budget = budget;
             as.reserved = reserved;
             as.retired = pool_bytes;
-            as.running = (int)active.size();
-            as.max_active = max_active;
+            as.running = (int)active.size() + (staged ? 1 : 0);
+            as.max_active = max_active + 1;
             const awe::AdmitResult ar =
-                awe::admit_fifo(as, stop ? 0 : (int)queue.size(), [&](int i) { return queue[i]->bytes; });
+                awe::admit_fifo(as, (stop || staged) ? 0 : (int)queue.size(), [&](int i) { return queue[i]->bytes; });
             flush = ar.free_retired;
             for (int i = 0; i < ar.count; ++i) {
                 Request* r = queue.front();
@@ -315,20 +389,25 @@ void awe_server_s::run() {
             free_pool();
             continue;
         }
+        bool progressed = promote();
         for (Request* r : admitted) {
             std::string err;
-            bool idle;
+            bool idle, slot;
             {
                 std::lock_guard<std::mutex> lk(mu);
-                idle = active.empty();
+                idle = active.empty() && !staged;
+                slot = (int)active.size() < max_active;
             }
-            if (start(r, idle, err)) {
+            if (!slot) {   // the admission leaves at most one request beyond max_active
+                stage(r);
+            } else if (start(r, idle, err)) {
                 std::lock_guard<std::mutex> lk(mu);
                 r->t[2] = now_s(t0);
                 active.push_back(r);
             } else {
                 finish(r, AWE_REQ_FAILED, err);
             }
+            progressed = true;
         }
         // keep two chunks in flight per running request; retire on completion
         std::vector<Request*> running;
@@ -336,7 +415,8 @@ void awe_server_s::run() {
             std::lock_guard<std::mutex> lk(mu);
             running = active;
         }
-        bool progressed = !admitted.empty();
+        // a staged request still uploading shares the device: no shape timing then
+        const bool quiet = !staged || staged->ready.load(std::memory_order_acquire);
         for (Request* r : running) {
             std::string err;
             bool failed = false;
@@ -353,25 +433,28 @@ void awe_server_s::run() {
                 --r->inflight;
                 progressed = true;
             }
-            while (!failed && r->inflight < 2 && r->phase != Request::kDone) {
-                if (advance_request(r, chunk, running.size() == 1)) {
-                    err = awe_last_error();
-                    failed = true;
-                    break;
-                }
-                const hipError_t e = hipEventRecord(r->ev[r->ev_head], r->stream);
-                if (e != hipSuccess) {
-                    err = hipGetErrorString(e);
-                    failed = true;
-                    break;
-                }
-                r->ev_head = (r->ev_head + 1) % 2;
-                ++r->inflight;
+            if (!failed && r->inflight < 2 && r->phase != Request::kDone) {
+                failed = !pump(r, err, running.size() == 1 && quiet);
                 progressed = true;
             }
-            bool done = false;
-            if (!failed && r->phase == Request::kDone && r->inflight == 0) {
-                // every step has completed, so the copy-out waits for nothing else
+            if (!failed && !(r->phase == Request::kDone && r->inflight == 0)) continue;
+            // r is finished: the staged request takes its slot and gets its
+            // first chunks before r's traces are copied out
+            { std::lock_guard<std::mutex> lk(mu); active.erase(std::find(active.begin(), active.end(), r)); }
+            if (promote()) {
+                Request* p;
+                {
+                    std::lock_guard<std::mutex> lk(mu);
+                    p = active.back();
+                }
+                std::string perr;
+                if (!pump(p, perr, false)) {
+                    { std::lock_guard<std::mutex> lk(mu); active.erase(std::find(active.begin(), active.end(), p)); }
+                    finish(p, AWE_REQ_FAILED, perr);
+                }
+            }
+            if (!failed) {
+                // every step of r has completed, so the copy-out waits for nothing else of r
                 const size_t ntr = (size_t)r->g.nt * r->g.nrec;
                 hipError_t e = hipSuccess;
                 if (ntr && r->traces_host)
@@ -383,13 +466,9 @@ void awe_server_s::run() {
                     err = hipGetErrorString(e);
                     failed = true;
                 }
-                done = true;
             }
-            if (failed || done) {
-                { std::lock_guard<std::mutex> lk(mu); active.erase(std::find(active.begin(), active.end(), r)); }
-                finish(r, failed ? AWE_REQ_FAILED : AWE_REQ_DONE, err);
-                progressed = true;
-            }
+            finish(r, failed ? AWE_REQ_FAILED : AWE_REQ_DONE, err);
+            progressed = true;
         }
         if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(20));
         std::lock_guard<std::mutex> lk(mu);

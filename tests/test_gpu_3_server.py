@@ -305,3 +305,32 @@ def test_repeated_gradient_requests_reuse_pooled_buffers_bit_for_bit():
         time.sleep(0.01)
     assert srv.stats()["bytes_reserved"] == 0
     srv.close()
+
+
+@pytest.mark.parametrize("max_active", [1, 2])
+def test_requests_set_up_ahead_start_in_arrival_order(max_active):
+    # with max_active requests running, the next one is set up ahead on a
+    # host thread of its own; requests must still start in arrival order
+    # (nothing is admitted past the one set up ahead) and give the bits they
+    # give alone
+    import paper_1608_08658_amd as awe
+    reqs = _requests(47, 6, scale=0.1)
+    srv = awe.Server(hbm_fraction=0.5, chunk_steps=8, max_active=max_active)
+    subs = [srv.submit(_geom(shot, dt), shot.m, w) for shot, dt, w in reqs]
+    for t, _ in subs:
+        srv.wait(t, timeout=300)
+    assert srv.stats()["completed"] == len(reqs) and srv.stats()["failed"] == 0
+    times = [srv.poll(t)[1] for t, _ in subs]
+    for i, tm in enumerate(times):
+        log(f"  request {i}: admitted {tm[1]:.4f} started {tm[2]:.4f} done {tm[3]:.4f}")
+        assert tm[0] <= tm[1] <= tm[2] <= tm[3]
+    starts = [tm[2] for tm in times]
+    assert starts == sorted(starts)
+    # at most max_active + 1 requests are admitted and not done: request j is
+    # admitted only after j - max_active of the earlier ones are done
+    for j in range(max_active + 1, len(times)):
+        done_before = sum(1 for k in range(j) if times[k][3] <= times[j][1])
+        assert done_before >= j - max_active, (j, done_before)
+    for (shot, dt, w), (t, tr) in zip(reqs, subs):
+        assert np.array_equal(tr.astype(np.float64), _alone(shot, dt, w)), shot.name
+    srv.close()
