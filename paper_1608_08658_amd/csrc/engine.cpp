@@ -562,29 +562,35 @@ struct TuneKey {
         return std::tie(dev, ndim, half, img, n0, n1, n2) < std::tie(o.dev, o.ndim, o.half, o.img, o.n0, o.n1, o.n2);
     }
 };
+struct TuneEntry {
+    LaunchShape shape;
+    bool timed;     // false: borrowed from a nearby size
+};
 std::mutex g_tune_mu;
-std::map<TuneKey, LaunchShape> g_tune_cache;
+std::map<TuneKey, TuneEntry> g_tune_cache;
 // Smallest grids worth timing: a 3-D tuning pass costs ~100 stencil launches
 // of the plan's own size, a 2-D pass a few milliseconds at most.
 constexpr int64_t kTuneMinPoints3 = 4 << 20;
 constexpr int64_t kTuneMinPoints2 = 1 << 16;
 
-// A shape tuned for a grid of the same dimensionality, order and mode with a
+// A shape timed for a grid of the same dimensionality, order and mode with a
 // point count within 30%, if there is one: taken instead of timing again (a
 // server meets many nearby sizes).  The window is narrow because the best
 // shape changes where the fields outgrow the 256 MB Infinity Cache (between
-// 336^3 and 380^3 at order 8).
+// 336^3 and 380^3 at order 8); even inside it a borrowed shape can be ~10%
+// slower than the size's own, so plans that run long time their own.
 bool nearby_shape(const TuneKey& key, LaunchShape& out) {
     const double pts = (double)key.n0 * key.n1 * key.n2;
     double best = 1.3;
     bool found = false;
     for (const auto& kv : g_tune_cache) {
         const TuneKey& o = kv.first;
+        if (!kv.second.timed) continue;
         if (o.dev != key.dev || o.ndim != key.ndim || o.half != key.half || o.img != key.img) continue;
         const double r = std::max(pts, (double)o.n0 * o.n1 * o.n2) / std::min(pts, (double)o.n0 * o.n1 * o.n2);
         if (r <= best) {
             best = r;
-            out = kv.second;
+            out = kv.second.shape;
             found = true;
         }
     }
@@ -620,19 +626,22 @@ awe_status Plan::tune(bool img, hipStream_t user_stream) {
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(key);
-        if (it != g_tune_cache.end()) {
-            shape = it->second;
+        LaunchShape near{};
+        const bool nearby = g.ndim == 3 && nearby_shape(key, near);
+        const ShapeSource src = shape_source(it != g_tune_cache.end(), it != g_tune_cache.end() && it->second.timed,
+                                             nearby, timed_tune, own_tune);
+        if (src == ShapeSource::kCached) {
+            shape = it->second.shape;
             return AWE_OK;
         }
-        LaunchShape near{};
-        if (g.ndim == 3 && nearby_shape(key, near)) {
+        if (src == ShapeSource::kBorrowed) {
             near.zchunk = balanced_zchunk(L.n[0], near.zchunk);   // the same chunk count, even here
             shape = near;
-            g_tune_cache[key] = near;
+            g_tune_cache[key] = {near, false};
             return AWE_OK;
         }
+        if (src == ShapeSource::kBuiltin) return AWE_OK;
     }
-    if (!timed_tune) return AWE_OK;   // the built-in shape
     std::vector<LaunchShape> cand;
     if (g.ndim == 3) {
         // chunks shorter than 28 planes only for the plain step: timed alone
@@ -693,7 +702,7 @@ awe_status Plan::tune(bool img, hipStream_t user_stream) {
     if (st) return st;
     shape = best;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[key] = best;
+    g_tune_cache[key] = {best, true};
     return AWE_OK;
 }
 

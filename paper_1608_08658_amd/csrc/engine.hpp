@@ -210,6 +210,8 @@ struct awe_plan_s {
     double* d_mpart = nullptr;
     hipStream_t setup_stream = nullptr;   // stream of init's fills and uploads
     bool timed_tune = true;         // false: take a cached or nearby launch shape, never time candidates
+    bool own_tune = true;           // with timed_tune: time this size's own shape rather than borrow a
+                                    // nearby size's (server forward requests borrow)
 
     // wavefield state: u[n] and u[n-1]
     const float* cur = nullptr;

@@ -234,6 +234,10 @@ bool awe_server_s::start(Request* r, bool idle, std::string& err) {
     try {
         r->plan = new awe_plan_s();
         r->plan->pool = &pool;   // buffers of earlier requests of the same grid are reused
+        // a gradient request (long, and typically one of many shots on one
+        // grid) times its own size's shapes when it may; forward requests
+        // take a nearby size's
+        r->plan->own_tune = r->gradient;
         st = r->plan->init(&r->g, r->stream, idle);
     } catch (const std::bad_alloc&) {
         st = fail(AWE_ENOMEM, "host allocation failed");

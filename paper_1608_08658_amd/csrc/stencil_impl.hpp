@@ -212,8 +212,11 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk, FusedSparse fs) {
     const auto r_gr = slab_rsrc(MODE != kStepPlain ? a.grad + slab : a.out + slab, bytes);
     const uint32_t plane = (uint32_t)(sz * 4);     // bytes per z plane
     auto soff = [&](int z) { return (uint32_t)(z - z0 + M) * plane; };
-    // Byte offsets from the slab base: the column goes in the per-lane vector
-    // offset, the row (wave-uniform) joins the plane in the scalar offset.
+    // Byte offsets from the slab base: column and row go in the per-lane
+    // vector offset (one register per row, set once), the plane in the
+    // scalar offset, so a load needs no address arithmetic and the rows hold
+    // no scalar registers (with the 3M+2 stencil coefficients in scalar
+    // registers, per-row scalar offsets made the compiler spill them).
     // Loads stay inside the allocation by construction: columns and rows are
     // clamped to the last ghost column / row, and no owned point uses a value
     // loaded from beyond them.  Lanes that own no point get kOob for the
@@ -225,17 +228,30 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk, FusedSparse fs) {
     uint32_t s_row[RY];
 #pragma unroll
     for (int r = 0; r < RY; ++r) s_row[r] = rowb(y0 + r);
-    // per-row store offsets (kOob where the row owns no point): a branch per
-    // row would split the unrolled plane into blocks the scheduler cannot mix
-    uint32_t v_str[RY];
+    // per-row offsets: stores (kOob where the row owns no point: a branch per
+    // row would split the unrolled plane into blocks the scheduler cannot
+    // mix), arrays read at owned points, and the wavefield.  The empty asm
+    // keeps each in a vector register instead of being recomputed per load.
+    uint32_t v_str[RY], v_pvr[RY], v_ldr[RY];
 #pragma unroll
-    for (int r = 0; r < RY; ++r) v_str[r] = (y0 + r < g.ny) ? v_st : kOob;
+    for (int r = 0; r < RY; ++r) {
+        v_str[r] = (y0 + r < g.ny && x < g.nx) ? v_st + s_row[r] : kOob;
+        v_pvr[r] = x < g.nx ? v_st + s_row[r] : kOob;
+        v_ldr[r] = v_ld + s_row[r];
+        asm volatile("" : "+v"(v_str[r]), "+v"(v_pvr[r]), "+v"(v_ldr[r]));
+    }
     // x halo: lanes tx < M of the first wave column load the left columns,
     // lanes tx >= 64-M of the last the right ones.
     const bool hl = wx == 0 && tx < M;
     const bool hr = wx == BX - 1 && tx >= kTileX - M;
     const int hlx = hl ? tx : (lxb + tx + 2 * M);  // LDS column of the halo value
     const uint32_t v_hx = (hl || hr) ? colb(hl ? x - M : x + M) : kOob;
+    uint32_t v_hxr[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        v_hxr[r] = (hl || hr) ? v_hx + s_row[r] : kOob;
+        asm volatile("" : "+v"(v_hxr[r]));
+    }
     // y halo: 2M rows (M above, M below the tile); thread row ty loads halo
     // rows h = ty, ty + BY, ... < 2M in its wave's 64 columns.
     int hyrow[NH];
@@ -246,6 +262,12 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk, FusedSparse fs) {
         const int y = (h < M) ? (yb - M + h) : (yb + TY + (h - M));
         hyrow[i] = (h < M) ? h : (TY + h);
         s_hy[i] = rowb(y);
+    }
+    uint32_t v_hyr[NH];
+#pragma unroll
+    for (int i = 0; i < NH; ++i) {
+        v_hyr[i] = v_ld + s_hy[i];
+        asm volatile("" : "+v"(v_hyr[i]));
     }
 
     const float exv = x < g.nx ? a.eta_x[x] : 0.f;
@@ -268,7 +290,7 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk, FusedSparse fs) {
 #pragma unroll
     for (int j = 1; j < NQ; ++j)
 #pragma unroll
-        for (int r = 0; r < RY; ++r) q[r][j] = bload(r_uc, v_ld, soff(z0 - M + j - 1) + s_row[r]);
+        for (int r = 0; r < RY; ++r) q[r][j] = bload(r_uc, v_ldr[r], soff(z0 - M + j - 1));
     drain_vmem();
 
     // what fetch(z) loads for plane z: the queue head uc(z + M), u_prev, C
@@ -284,20 +306,20 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk, FusedSparse fs) {
         const uint32_t so = soff(z), sf = soff(z + M);
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-            P.fr[r] = bload(r_uc, v_ld, sf + s_row[r]);
+            P.fr[r] = bload(r_uc, v_ldr[r], sf);
             // arrays read only at owned points: lanes past the grid read
             // nothing (a clamped column can sit in a line of its own)
-            P.pv[r] = bload<AWE_CPOL_STREAM>(r_up, v_st, so + s_row[r]);
-            P.cv[r] = bload<AWE_CPOL_STREAM>(r_cf, v_st, so + s_row[r]);
+            P.pv[r] = bload<AWE_CPOL_STREAM>(r_up, v_pvr[r], so);
+            P.cv[r] = bload<AWE_CPOL_STREAM>(r_cf, v_pvr[r], so);
             if (MODE == kStepImaging || MODE == kStepBorn) {
-                P.sv[r] = bload<AWE_CPOL_STREAM>(r_us, v_st, so + s_row[r]);
-                P.gv[r] = bload<AWE_CPOL_STREAM>(r_gr, v_st, so + s_row[r]);
+                P.sv[r] = bload<AWE_CPOL_STREAM>(r_us, v_pvr[r], so);
+                P.gv[r] = bload<AWE_CPOL_STREAM>(r_gr, v_pvr[r], so);
             }
-            P.hxv[r] = bload(r_uc, v_hx, so + s_row[r]);
+            P.hxv[r] = bload(r_uc, v_hxr[r], so);
         }
 #pragma unroll
         for (int i = 0; i < NH; ++i)
-            if (kHyFull || ty + i * BY < 2 * M) P.hyv[i] = bload(r_uc, v_ld, so + s_hy[i]);
+            if (kHyFull || ty + i * BY < 2 * M) P.hyv[i] = bload(r_uc, v_hyr[i], so);
     };
 #pragma unroll
     for (int i = 0; i < PF; ++i)
@@ -333,8 +355,14 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk, FusedSparse fs) {
             if (MODE == kStepImaging || MODE == kStepBorn) { s[r] = P.sv[r]; gg[r] = P.gv[r]; }
         }
         const float ezv = P.ezn;
-        // the set is consumed: refill it with plane z + PF
-        if (z + PF < z1) fetch(P, z + PF);
+        // the set is consumed: refill it with plane z + PF.  The order-16
+        // plain step refills without a branch (past the chunk's end it loads
+        // the last plane again, unused), since the join of the branch costs
+        // register moves of the whole set: 404 -> 381 us per 480^3 step in
+        // the best launch shape.  At orders 10-14 and with imaging the
+        // branch-free form was measured slower.
+        if constexpr (M == 8 && MODE == kStepPlain) fetch(P, min(z + PF, z1 - 1));
+        else if (z + PF < z1) fetch(P, z + PF);
         lds_barrier();
 
         const uint32_t so = soff(z);
@@ -368,9 +396,9 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk, FusedSparse fs) {
             const float av = (ezv + eyv[r] + exv) * c[r] * k.inv_dt;
             float t = c[r] * lap + av * (p[r] - u0);
             if (MODE == kStepBorn) t -= (c[r] * k.inv_dt2) * (s[r] * gg[r]);
-            bstore<AWE_CPOL_STREAM>(r_out, (u0 - p[r]) + u0 + t, v_str[r], so + s_row[r]);
-            if (MODE == kStepImaging) bstore<AWE_CPOL_STREAM>(r_gr, gg[r] + s[r] * t, v_str[r], so + s_row[r]);
-            if (MODE == kStepSaveT) bstore<AWE_CPOL_STREAM>(r_gr, t, v_str[r], so + s_row[r]);
+            bstore<AWE_CPOL_STREAM>(r_out, (u0 - p[r]) + u0 + t, v_str[r], so);
+            if (MODE == kStepImaging) bstore<AWE_CPOL_STREAM>(r_gr, gg[r] + s[r] * t, v_str[r], so);
+            if (MODE == kStepSaveT) bstore<AWE_CPOL_STREAM>(r_gr, t, v_str[r], so);
         }
     };
     // before plane z0 the queue holds planes z0-M .. z0+M-1 in physical slots

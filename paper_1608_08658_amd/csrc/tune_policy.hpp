@@ -30,6 +30,21 @@ int pick_timed_shape(size_t n, const float* t, ZchunkOf zchunk_of, float tie = 0
     return best;
 }
 
+// Where a plan's launch shape comes from.  exact: the cache holds an entry
+// for this very size (exact_timed: timed, not borrowed); nearby: it holds a
+// timed entry for a size within the borrowing window; may_time: the plan may
+// time candidates now (no other work on the device); own: the plan runs long
+// enough to repay timing its own size (plans made directly and gradient
+// requests; a server's forward requests borrow instead, since a server meets
+// many sizes and timing each costs ~100 launches of it).
+enum class ShapeSource { kCached, kBorrowed, kTimed, kBuiltin };
+inline ShapeSource shape_source(bool exact, bool exact_timed, bool nearby, bool may_time, bool own) {
+    const bool time_own = may_time && own;
+    if (exact && (exact_timed || !time_own)) return ShapeSource::kCached;
+    if (nearby && !time_own) return ShapeSource::kBorrowed;
+    return may_time ? ShapeSource::kTimed : ShapeSource::kBuiltin;
+}
+
 // The z-chunk of the same chunk count as `zc` over nz planes with the chunks
 // as equal as possible: ceil(nz / ceil(nz / zc)).  A grid of 150 planes cut
 // into 28-plane chunks ends with a 10-plane chunk that pays the same warm-up

@@ -1,7 +1,8 @@
 // CPU checks of the autotuner's choice of launch shape (tune_policy.hpp):
 // fixed cases (a clear winner, ties settled by the longer z-chunk and then
 // the faster, the tie boundary, nothing timed) and seeded random timings
-// checked against the properties that define the choice.  Prints "ok" or
+// checked against the properties that define the choice; balanced z-chunks;
+// and where a plan's shape comes from (cached, borrowed, timed, built-in).  Prints "ok" or
 // the failed check and exits non-zero on failure.
 #include <cstdio>
 #include <random>
@@ -81,6 +82,35 @@ int main() {
             CHECK(nz - (n1 - 1) * b >= b - n1);        // the last chunk is short by less than the count
             if (fails) break;
         }
+    // where a plan's shape comes from (shape_source): the whole truth table,
+    // checked against the rule's statement rather than its code
+    using awe::ShapeSource;
+    for (int bits = 0; bits < 32; ++bits) {
+        const bool exact = bits & 1, exact_timed = exact && (bits & 2), nearby = bits & 4, may_time = bits & 8,
+                   own = bits & 16;
+        const ShapeSource s = awe::shape_source(exact, exact_timed, nearby, may_time, own);
+        // a timed entry for the size itself is always used
+        if (exact_timed) CHECK(s == ShapeSource::kCached);
+        // nothing is timed unless the plan may time
+        if (!may_time) CHECK(s != ShapeSource::kTimed);
+        // a plan that may time and repays it never runs a borrowed shape
+        if (may_time && own) CHECK(s == ShapeSource::kCached ? exact_timed : s == ShapeSource::kTimed);
+        // a plan that does not repay timing borrows before it times
+        if (!own && !exact && nearby) CHECK(s == ShapeSource::kBorrowed);
+        // and reuses what its size already has, borrowed or not
+        if (!own && exact) CHECK(s == ShapeSource::kCached);
+        // with nothing cached and nothing near: time if allowed, else the built-in shape
+        if (!exact && !nearby) CHECK(s == (may_time ? ShapeSource::kTimed : ShapeSource::kBuiltin));
+        if (!may_time && !exact && !nearby) CHECK(s == ShapeSource::kBuiltin);
+    }
+    // the served-gradient sequence: a serving mix left a borrowed entry for the
+    // size; the first gradient request (idle) times its own, the later ones
+    // (set up among running work) reuse that timed entry
+    CHECK(awe::shape_source(true, false, true, true, true) == ShapeSource::kTimed);
+    CHECK(awe::shape_source(true, true, true, false, true) == ShapeSource::kCached);
+    // a forward request of a new nearby size, idle or not, borrows
+    CHECK(awe::shape_source(false, false, true, true, false) == ShapeSource::kBorrowed);
+    CHECK(awe::shape_source(false, false, true, false, false) == ShapeSource::kBorrowed);
     if (fails) return 1;
     std::printf("ok\n");
     return 0;

@@ -205,12 +205,12 @@ def test_autotuned_2d_plan_matches_forced_shape(monkeypatch, order):
         assert np.array_equal(tuned[0], forced[0]) and np.array_equal(tuned[1], forced[1]), cfg
 
 
-def test_nearby_3d_sizes_reuse_a_tuned_shape(monkeypatch):
-    # a second plan within 30% of a tuned size (in points) takes its shape
-    # without timing; its results equal a forced run of that shape
-    import paper_1608_08658_amd as awe
+def test_nearby_3d_sizes_each_get_a_shape_with_the_same_results(monkeypatch):
+    # plans made directly time their own size even next to a tuned nearby
+    # size (the rule is checked on the CPU, tests/cpp/tune_policy_check.cpp);
+    # whatever shape each takes, its traces equal a forced run of the
+    # built-in shape bit for bit
     rng = np.random.default_rng(6)
-    outs = []
     for n in (150, 156):
         shape = (n, n, n)
         v = synth.layered_velocity(shape, rng, nlayers=(3, 5))
@@ -218,13 +218,10 @@ def test_nearby_3d_sizes_reuse_a_tuned_shape(monkeypatch):
                           np.array([[300.0, 700.0, 700.0]]), np.array([[25.0, 100.0, 900.0]]), 20.0,
                           damp_vref=float(v.min()))
         dt = shot_dt(shot)
-        for k in ("AWE_TILE", "AWE_AUTOTUNE"):
-            monkeypatch.delenv(k, raising=False)
-        plan = gpu_plan(shot, dt)
-        outs.append(plan.info()["forward_shape"])
-        plan.close()
-    log(f"tuned {outs[0]}, reused {outs[1]}")
-    assert outs[0] == outs[1]
+        tuned = _forward_with_env(monkeypatch, shot, dt, {"AWE_TILE": None, "AWE_AUTOTUNE": None})
+        forced = _forward_with_env(monkeypatch, shot, dt, {"AWE_TILE": None, "AWE_AUTOTUNE": "0"})
+        log(f"n={n}: tuned and built-in shapes give equal traces")
+        assert np.array_equal(tuned[0], forced[0]) and np.array_equal(tuned[1], forced[1])
 
 
 @pytest.mark.parametrize("kind", ["2d", "3d"])
