@@ -57,19 +57,24 @@ def kernel_source_digest(path=KERNEL_SRC):
 
 def profiled_traffic(shape, path=PROFILE):
     """HBM bytes per stencil launch from a committed rocprofv3 counter
-    summary, or None when the kernel code or launch shape has changed since
-    the counters were taken."""
+    summary (one entry per launch shape that was profiled), or None when the
+    kernel code has changed since the counters were taken or this launch
+    shape was not profiled."""
     try:
-        facts = {}
+        digest, per_shape = None, {}
         for line in open(path):
-            if ":" in line and line.startswith("    ") and not line.strip().startswith(("cd ", "|")):
-                k, v = line.strip().split(":", 1)
-                facts[k.strip()] = v.split()[0] if v.split() else ""
-        sha = kernel_source_digest()
-        if facts.get("source_digest") != sha or facts.get("launch_shape") != f"{shape[0]},{shape[1]}":
+            t = line.strip()
+            if not line.startswith("    "):
+                continue
+            if t.startswith("source_digest:"):
+                digest = t.split()[1]
+            elif t.startswith("shape ") and "traffic_bytes_per_launch" in t:
+                f = t.split()
+                per_shape[f[1].rstrip(":")] = float(f[f.index("traffic_bytes_per_launch") + 1])
+        if digest != kernel_source_digest():
             return None
-        return float(facts["traffic_bytes_per_launch"])
-    except (OSError, KeyError, ValueError):
+        return per_shape.get(f"{shape[0]},{shape[1]}")
+    except (OSError, ValueError, IndexError):
         return None
 
 

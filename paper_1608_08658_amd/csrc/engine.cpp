@@ -464,7 +464,6 @@ awe_status Plan::init(const awe_geometry* geo, hipStream_t setup, bool timed) {
         ey.assign(1, 0.0);
         ex = damping_axis(g.shape[1], g.nbl, g.spacing[1], g.damp_power, g.damp_R, g.damp_vref);
     }
-    auto tof = [](const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); };
 
     // off-grid tables
     PointTable ts, tr;
@@ -478,7 +477,14 @@ awe_status Plan::init(const awe_geometry* geo, hipStream_t setup, bool timed) {
     AWE_HIP(hipGetDevice(&dev));
     device = dev;
     if ((st = upload(&d_ezd, ez)) || (st = upload(&d_eyd, ey)) || (st = upload(&d_exd, ex))) return st;
-    if ((st = upload(&d_ez, tof(ez))) || (st = upload(&d_ey, tof(ey))) || (st = upload(&d_ex, tof(ex)))) return st;
+    // the step kernels read eta / dt (one multiply fewer per point update)
+    auto over_dt = [&](const std::vector<double>& v) {
+        std::vector<float> o(v.size());
+        for (size_t i = 0; i < v.size(); ++i) o[i] = (float)(v[i] / g.dt);
+        return o;
+    };
+    if ((st = upload(&d_ez, over_dt(ez))) || (st = upload(&d_ey, over_dt(ey))) || (st = upload(&d_ex, over_dt(ex))))
+        return st;
     if ((st = upload(&src_node, ts.node)) || (st = upload(&src_w, ts.w))) return st;
     if ((st = upload(&rec_node, tr.node)) || (st = upload(&rec_w, tr.w))) return st;
     if ((st = upload(&src_csr.node, cs.node)) || (st = upload(&src_csr.rowptr, cs.rowptr)) ||

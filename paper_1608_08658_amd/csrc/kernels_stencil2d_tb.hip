@@ -83,7 +83,7 @@ step2d_tb(const float* __restrict__ uc, const float* __restrict__ up, float* __r
                 lu[di][j] = in ? uc[gi] : 0.f;
                 lp[di][j] = in ? up[gi] : 0.f;
                 cf[i][j] = in ? c : 0.f;
-                av[i][j] = in ? ev * c * k.inv_dt : 0.f;
+                av[i][j] = in ? ev * c : 0.f;   // the tables hold eta / dt
             }
         }
 #pragma unroll
@@ -179,8 +179,10 @@ step2d_tb(const float* __restrict__ uc, const float* __restrict__ up, float* __r
                     }
                     const float pv = prv[e];
                     const float c = cf[i][j];
-                    const float t = c * lap + av[i][j] * (pv - u0);
-                    nv[di][j] = (u0 - pv) + u0 + t;
+                    // the update of step2d, rounding for rounding
+                    const float d = pv - u0;
+                    const float t = __builtin_fmaf(c, lap, av[i][j] * d);
+                    nv[di][j] = (u0 - d) + t;
                 }
             }
 #pragma unroll

@@ -5,6 +5,10 @@
 //   t   = C * L_P(uc) + a * (up - uc),        a = (eta_z + eta_y + eta_x) * C / dt
 //   out = 2 uc - up + t                        (= (2-a) uc - (1-a) up + C L_P uc)
 //
+// The damping tables the kernels read hold eta / dt (scaled on the host), and
+// 2 uc - up is formed as uc - (up - uc) from the difference the damping term
+// uses: rounding of -(a - b) and b - a is the same, so this is (uc - up) + uc.
+//
 // Modes (template parameter MODE, see StepMode):
 //   plain    just the update above;
 //   imaging  grad += usnap * t            (t = mu[n] - 2 mu[n+1] + mu[n+2] without
@@ -379,6 +383,7 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk, FusedSparse fs) {
             asm volatile("" : "+v"(lrow[r]));
         }
         const float* lflat = &lds[0][0][0];
+        const float ezx = ezv + exv;
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             const float* ly = lflat + lofs + (r + M) * LW;   // this point, y pairs
@@ -393,10 +398,15 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk, FusedSparse fs) {
                 lap += k.cx[kk] * (lx[-kk] + lx[kk]);
             }
             const float u0 = Q(r, M);
-            const float av = (ezv + eyv[r] + exv) * c[r] * k.inv_dt;
-            float t = c[r] * lap + av * (p[r] - u0);
+            const float d = p[r] - u0;
+            const float av = (ezx + eyv[r]) * c[r];
+            // the Laplacian term's product is the exact one (the larger term;
+            // fusing the damping product instead raised the GPU dot-test
+            // error at order 16 to 1.5e-5); written out so the 2-D kernels
+            // round alike
+            float t = __builtin_fmaf(c[r], lap, av * d);
             if (MODE == kStepBorn) t -= (c[r] * k.inv_dt2) * (s[r] * gg[r]);
-            bstore<AWE_CPOL_STREAM>(r_out, (u0 - p[r]) + u0 + t, v_str[r], so);
+            bstore<AWE_CPOL_STREAM>(r_out, (u0 - d) + t, v_str[r], so);
             if (MODE == kStepImaging) bstore<AWE_CPOL_STREAM>(r_gr, gg[r] + s[r] * t, v_str[r], so);
             if (MODE == kStepSaveT) bstore<AWE_CPOL_STREAM>(r_gr, t, v_str[r], so);
         }
@@ -524,10 +534,11 @@ step2d(StepArgs a, StencilCoef k, Geo2 g, int zchunk, FusedSparse fs) {
                 lap += k.cx[kk] * (lds[b][w][lx - kk] + lds[b][w][lx + kk]);
             }
             const float u0 = q[M];
-            const float av = (ezv + exv) * c * k.inv_dt;
-            float t = c * lap + av * (p - u0);
+            const float d = p - u0;
+            const float av = (ezv + exv) * c;
+            float t = __builtin_fmaf(c, lap, av * d);   // as in step2d_tb
             if (MODE == kStepBorn) t -= (c * k.inv_dt2) * (s * gg);
-            bstore<AWE_CPOL_STREAM>(r_out, (u0 - p) + u0 + t, o_in, soff(z));
+            bstore<AWE_CPOL_STREAM>(r_out, (u0 - d) + t, o_in, soff(z));
             if (MODE == kStepImaging) bstore<AWE_CPOL_STREAM>(r_gr, gg + s * t, o_in, soff(z));
             if (MODE == kStepSaveT) bstore<AWE_CPOL_STREAM>(r_gr, t, o_in, soff(z));
         }
