@@ -320,7 +320,7 @@ void awe_server_s::stage(Request* r) {
 bool awe_server_s::promote() {
     Request* r = staged;
     if (!r || !r->ready.load(std::memory_order_acquire)) return false;
-    {
+    if (r->setup_ok) {   // a failed set-up retires at once, without waiting for a slot
         std::lock_guard<std::mutex> lk(mu);
         if ((int)active.size() >= max_active) return false;
     }
