@@ -102,34 +102,25 @@ def test_forward_resumes_from_state_bitwise():
     assert np.array_equal(host(tr), full)
 
 
-def test_full_size_state_steps_sampled():
-    # At the full 3-D forward size (256^3 + 40-point layer, order 8) and in the
-    # launch shape the benchmark uses: three steps from a seeded smooth random
-    # state, compared point by point with the oracle evaluated on small
-    # sub-blocks around sampled points (corners, faces, the layer, tile seams,
-    # the source).
-    shot = synth.config_3d_forward(nt=4)
+def _state_steps_sampled(shot, pts, seed=42, nsteps=3):
+    """nsteps GPU steps from a seeded smooth random state, compared point by
+    point with the oracle evaluated on small sub-blocks around the points."""
     dt = shot_dt(shot)
-    rng = np.random.default_rng(42)
-    P = shot.padded = tuple(n + 2 * shot.nbl for n in shot.shape)
-    log(f"case full-size state steps {P}")
+    rng = np.random.default_rng(seed)
+    P = tuple(n + 2 * shot.nbl for n in shot.shape)
     u0 = synth.random_state(rng, P, 3.0).astype(np.float32)
     um = (u0 * 0.999).astype(np.float32)
     plan = gpu_plan(shot, dt)
     plan.set_model(dev(shot.m))
     w = shot.wavelet(dt) * 1e3
     plan.set_state(dev(u0), dev(um))
-    nsteps = 3
     plan.step(0, nsteps, dev(w), None)
     u, _ = plan.get_state()
     u = host(u)
+    log(f"  launch shape {plan.info()['forward_shape']}")
     plan.close()
     op = oracle.Operator(oracle_problem(shot, dt, nt=nsteps + 1), shot.m)
-    M = shot.order // 2
-    r = nsteps * M
-    s_node = np.floor(shot.src_coords[0] / np.array(shot.spacing) + shot.nbl).astype(int)
-    pts = [(0, 0, 0), (P[0] - 1, P[1] - 1, P[2] - 1), (0, 170, 63), (335, 64, 128), (40, 40, 40),
-           (167, 15, 16), (168, 16, 64), (200, 300, 335), (17, 200, 1), tuple(s_node), (100, 127, 191)]
+    r = nsteps * (shot.order // 2)
     from oracle.fd import laplacian
     from oracle.sparse import spread
     for p in pts:
@@ -150,6 +141,47 @@ def test_full_size_state_steps_sampled():
         scale = max(abs(want), 1e-3 * np.max(np.abs(u0)))
         log(f"  point {p}: gpu {got:.7e} oracle {want:.7e}")
         assert abs(got - want) <= 1e-5 * scale, p
+
+
+def _src_node(shot):
+    return tuple(np.floor(shot.src_coords[0] / np.array(shot.spacing) + shot.nbl).astype(int))
+
+
+def test_full_size_state_steps_sampled():
+    # At the full 3-D forward size (256^3 + 40-point layer, order 8) and in the
+    # launch shape the benchmark uses: three steps from a seeded smooth random
+    # state, compared point by point with the oracle evaluated on small
+    # sub-blocks around sampled points (corners, faces, the layer, tile seams,
+    # the source).
+    shot = synth.config_3d_forward(nt=4)
+    P = tuple(n + 2 * shot.nbl for n in shot.shape)
+    log(f"case full-size state steps {P}")
+    pts = [(0, 0, 0), (P[0] - 1, P[1] - 1, P[2] - 1), (0, 170, 63), (335, 64, 128), (40, 40, 40),
+           (167, 15, 16), (168, 16, 64), (200, 300, 335), (17, 200, 1), _src_node(shot), (100, 127, 191)]
+    _state_steps_sampled(shot, pts)
+
+
+@pytest.mark.parametrize("tile", [None, "3,30", "1,38"])
+def test_full_size_paper_example_state_steps_sampled(tile, monkeypatch):
+    # The paper's 3-D run (order 14, 150 x 281 x 281 computed: five 64-point x
+    # tiles, the last holding 25 columns) in the autotuned shape and in the
+    # shapes the tuner picks there: points at the corners, on z-chunk seams
+    # (multiples of 30 and 38), on tile-row seams (multiples of 8 and 16), on
+    # x-tile seams and in the ragged last x tile, in the layer, on the
+    # receiver line and at the source.
+    if tile is None:
+        monkeypatch.delenv("AWE_TILE", raising=False)
+    else:
+        monkeypatch.setenv("AWE_TILE", tile)
+    monkeypatch.delenv("AWE_AUTOTUNE", raising=False)
+    shot = synth.config_paper_example()
+    shot.nt = 4
+    P = tuple(n + 2 * shot.nbl for n in shot.shape)
+    log(f"case paper example state steps {P}, tile {tile}")
+    pts = [(0, 0, 0), (P[0] - 1, P[1] - 1, P[2] - 1), (29, 15, 63), (30, 16, 64), (37, 8, 127), (38, 135, 128),
+           (60, 128, 255), (75, 200, 256), (89, 271, 280), (90, 280, 270), (119, 47, 192), (120, 140, 191),
+           (42, 140, 1), (42, 140, 279), (149, 0, 280), _src_node(shot)]
+    _state_steps_sampled(shot, pts)
 
 
 def _forward_with_env(monkeypatch, shot, dt, env):
