@@ -417,6 +417,40 @@ def bench_small_2d(torch, awe, synth, reps=5):
             "grid_pt_updates_per_s": npad * (shot.nt - 1) / t, "finite": finite}
 
 
+def bench_two_steps_per_sweep(torch, awe, synth, pairs=20):
+    """The temporal-blocking prototype (two order-8 steps per z-sweep, no
+    point operators) against single steps on the 336^3 forward grid, from the
+    same seeded state; results are bit-identical (tested)."""
+    shot = synth.config_3d_forward(nt=2 * pairs + 1)
+    dt = shot.dt_factor * awe.dt_max(3, shot.order, shot.spacing, float(np.sqrt(1.0 / shot.m.min())))
+    plan = awe.Plan(shape=shot.shape, spacing=shot.spacing, space_order=shot.order, nbl=shot.nbl, dt=dt,
+                    nt=shot.nt, src_coords=np.zeros((0, 3)), rec_coords=np.zeros((0, 3)), damp_power=shot.damp_power,
+                    damp_R=shot.damp_R, damp_vref=shot.damp_vref)
+    plan.set_model(torch.tensor(shot.m, dtype=torch.float32, device="cuda"))
+    P = plan.padded
+    u0 = torch.tensor(synth.random_state(np.random.default_rng(9), P, 3.0), dtype=torch.float32, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    times = {}
+    for name, run in (("single", lambda: plan.step(0, 2 * pairs)), ("blocked", lambda: plan.step2_blocked(pairs))):
+        plan.set_state(u0, u0 * 0.999)
+        run()                                   # warm-up (the first blocked call allocates two fields)
+        plan.set_state(u0, u0 * 0.999)
+        ev[0].record()
+        run()
+        ev[1].record()
+        torch.cuda.synchronize()
+        times[name] = ev[0].elapsed_time(ev[1]) * 1e3 / (2 * pairs)
+    plan.close()
+    npad = int(np.prod(P))
+    log(f"two steps per sweep (prototype): {times['blocked']:.1f} us per step against {times['single']:.1f} us "
+        f"for single steps")
+    return {"workload": f"{2 * pairs} order-8 steps without point operators on the 336^3 forward grid, seeded state",
+            "single_step_us": times["single"], "two_per_sweep_us_per_step": times["blocked"],
+            "speedup": times["single"] / times["blocked"],
+            "single_frac": 16.0 * npad / (times["single"] * 1e-6) / 8e12,
+            "two_per_sweep_frac": 16.0 * npad / (times["blocked"] * 1e-6) / 8e12}
+
+
 def bench_paper_example(torch, awe, synth):
     """The paper's 3-D run (Sec. V.D): 281 x 281 x 150 computed points,
     h = 15 m, order 14, 10 Hz Ricker, 1 s modelled, synthetic layered model."""
@@ -473,6 +507,8 @@ def main():
     ap.add_argument("--paper-example", type=int, default=1, help="run the paper's 3-D example workload (0 = skip)")
     ap.add_argument("--born", type=int, default=1, help="time Born modelling on the forward grid (0 = skip)")
     ap.add_argument("--small-2d", type=int, default=1, help="time the small 2-D shot (0 = skip)")
+    ap.add_argument("--two-steps-per-sweep", type=int, default=1,
+                    help="time the temporal-blocking prototype against single steps (0 = skip)")
     ap.add_argument("--serve-requests", type=int, default=200, help="requests per serving point (0 = skip)")
     ap.add_argument("--serve-scale", type=float, default=1.0,
                     help="size/step scale of the serving mix (1 = the full mix; < 1 shrinks it for quick runs)")
@@ -576,6 +612,11 @@ def main():
         log("small 2-D workload ...")
         small = bench_small_2d(torch, awe, synth)
 
+    tb3 = None
+    if args.two_steps_per_sweep:
+        log("two steps per sweep (temporal-blocking prototype) ...")
+        tb3 = bench_two_steps_per_sweep(torch, awe, synth)
+
     born = None
     if args.born:
         log("Born modelling ...")
@@ -632,6 +673,7 @@ def main():
         "gradient": grad,
         "paper_example": paper,
         "small_2d": small,
+        "two_steps_per_sweep": tb3,
         "born": born,
         "serving": serve,
         "served_gradients": shots,

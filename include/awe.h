@@ -289,6 +289,18 @@ awe_status awe_get_gradient_padded(awe_plan plan, float* g_pad_dev, awe_stream s
 awe_status awe_set_state(awe_plan plan, const float* u_dev, const float* u_prev_dev, awe_stream stream);
 awe_status awe_step(awe_plan plan, int32_t n0, int32_t nsteps, const float* wavelet_dev,
                     float* traces_dev, awe_stream stream);
+/*
+ * Temporal blocking (Sec. VI discusses time tiling), a measured prototype:
+ * advances the state by 2 * npairs steps, two steps per z-sweep of one
+ * launch, with no point operators (the plan must have no sources; no traces
+ * are recorded).  The result is bit for bit what awe_step gives for the same
+ * steps; it is slower than awe_step on every grid measured, so no forward
+ * path uses it.  3-D plans of space order <= 8 with fields under 2 GB only
+ * (AWE_EINVAL otherwise; AWE_ESTATE before awe_set_model).  zchunk = z planes
+ * per workgroup (0: a built-in choice).  The first call allocates two more
+ * fields, not counted by awe_footprint.
+ */
+awe_status awe_step2_blocked(awe_plan plan, int32_t npairs, int32_t zchunk, awe_stream stream);
 awe_status awe_get_state(awe_plan plan, float* u_dev, float* u_prev_dev, awe_stream stream);
 
 /*

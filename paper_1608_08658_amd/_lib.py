@@ -58,6 +58,7 @@ _SIGNATURES = {
     "awe_get_gradient_padded": (_I32, [_P, _P, _P]),
     "awe_set_state": (_I32, [_P, _P, _P, _P]),
     "awe_step": (_I32, [_P, _I32, _I32, _P, _P, _P]),
+    "awe_step2_blocked": (_I32, [_P, _I32, _I32, _P]),
     "awe_get_state": (_I32, [_P, _P, _P, _P]),
     "awe_misfit": (_I32, [_P, _P, _I64, _P, C.POINTER(_D), _P]),
     "awe_misfit_noalloc": (_I32, [_P, _P, _I64, _P, _P, _P]),
@@ -77,7 +78,7 @@ def header_symbols() -> list[str]:
     """Every function name declared in include/awe.h."""
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(awe_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(awe_[a-z0-9_]+)\s*\(", text)))
 
 
 def _hip_runtimes_mapped() -> set[str]:

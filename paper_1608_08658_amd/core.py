@@ -251,6 +251,11 @@ class Plan:
                              _ptr(wavelet, "wavelet", (self.nt, self.nsrc), allow_none=True),
                              _ptr(traces, "traces", (self.nt, self.nrec), allow_none=True), _stream()))
 
+    def step2_blocked(self, npairs, zchunk=0):
+        """2 * npairs source-free steps, two per z-sweep (the temporal-blocking
+        prototype; bit-identical to step, and slower)."""
+        check(lib().awe_step2_blocked(self.handle, int(npairs), int(zchunk), _stream()))
+
     def get_state(self):
         torch = _torch()
         u = torch.empty(self.padded, dtype=torch.float32, device="cuda")

@@ -217,6 +217,11 @@ awe_status awe_step(awe_plan plan, int32_t n0, int32_t nsteps, const float* wave
     AWE_TRY(return plan->step(n0, nsteps, wavelet, traces, as_stream(s)));
 }
 
+awe_status awe_step2_blocked(awe_plan plan, int32_t npairs, int32_t zchunk, awe_stream s) {
+    AWE_PLAN(plan);
+    AWE_TRY(return plan->step2_blocked(npairs, zchunk, as_stream(s)));
+}
+
 awe_status awe_get_state(awe_plan plan, float* u, float* u_prev, awe_stream s) {
     AWE_PLAN(plan);
     if (u) AWE_HIP(awe::launch_pack(u, plan->cur, plan->L, 1.f, as_stream(s)));

@@ -138,6 +138,13 @@ int tb_tile();
 int tb_max_tile_receivers();
 // (uc, up) = (u[n0], u[n0-1]) -> (out_c, out_p) = (u[n0+nsteps], u[n0+nsteps-1]);
 // the outputs must be distinct from the inputs (tiles read halos of others).
+// Two 3-D plain steps per z-sweep without point operators, half-widths
+// 1..kTb3MaxHalf, fields under 2 GB (kernels_stencil3d_tb.hip): o1 = u[n+1],
+// o2 = u[n+2] from uc = u[n], up = u[n-1]; the outputs alias neither input.
+constexpr int kTb3MaxHalf = 4;
+hipError_t launch_step3d_tb2(const Layout& L, const StencilCoef& k, const float* uc, const float* up, float* o1,
+                             float* o2, const float* coef, const float* ez, const float* ey, const float* ex, int zchunk,
+                             hipStream_t s);
 hipError_t launch_step2d_tb(const Layout& L, const StencilCoef& k, const float* uc, const float* up, float* out_c,
                             float* out_p, const float* coef, const float* eta_z, const float* eta_x,
                             const TbPoints& p, int n0, int nsteps, hipStream_t s);

@@ -1034,6 +1034,39 @@ awe_status Plan::step(int n0, int nsteps, const float* wavelet, float* traces, h
     return AWE_OK;
 }
 
+// Two plain steps per z-sweep, npairs times (kernels_stencil3d_tb.hip): the
+// state (u[n], u[n-1]) becomes (u[n+2], u[n+1]) per launch, bit for bit what
+// two awe_step calls give for a plan without sources.  The outputs go to two
+// work fields other than the state's, which then become the state.
+awe_status Plan::step2_blocked(int npairs, int zchunk, hipStream_t s) {
+    if (!model_set) return fail(AWE_ESTATE, "awe_set_model has not been called on this plan");
+    if (g.ndim != 3 || half > kTb3MaxHalf)
+        return fail(AWE_EINVAL, "two steps per sweep are built for 3-D grids of space order <= %d", 2 * kTb3MaxHalf);
+    if (g.nsrc != 0) return fail(AWE_EINVAL, "two steps per sweep apply no point operators: the plan must have no sources");
+    if (L.total * 4 > 0x7FFFFFF0ll) return fail(AWE_EINVAL, "two steps per sweep need fields under 2 GB");
+    if (npairs < 0 || zchunk < 0) return fail(AWE_EINVAL, "npairs and zchunk must be >= 0");
+    if (npairs == 0) return AWE_OK;
+    const int zc = zchunk ? zchunk : balanced_zchunk(L.n[0], 56);
+    float* bufs[4] = {w0, w1, w2, w3};
+    for (int i = 2; i < 4; ++i)
+        if (!bufs[i]) {
+            const awe_status st = alloc_field(&bufs[i], s);
+            if (st) return st;
+        }
+    w2 = bufs[2];
+    w3 = bufs[3];
+    for (int p = 0; p < npairs; ++p) {
+        float* out[2];
+        int nout = 0;
+        for (float* b : bufs)
+            if (b != cur && b != prev && nout < 2) out[nout++] = b;
+        AWE_HIP(launch_step3d_tb2(L, k, cur, prev, out[0], out[1], coef, d_ez, d_ey, d_ex, zc, s));
+        prev = out[0];
+        cur = out[1];
+    }
+    return AWE_OK;
+}
+
 // Linearised (Born) modelling: J dm, the derivative of the traces with
 // respect to m in the direction dm.  The background u and the scattered field
 // du advance together: the background step also writes its second time

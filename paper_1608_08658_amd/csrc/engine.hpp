@@ -281,6 +281,7 @@ struct awe_plan_s {
     awe_status forward(const float* wavelet, float* traces, int K, hipStream_t s);
     awe_status forward_binomial(const float* wavelet, float* traces, int snapshots, hipStream_t s);
     awe_status step(int n0, int nsteps, const float* wavelet, float* traces, hipStream_t s);
+    awe_status step2_blocked(int npairs, int zchunk, hipStream_t s);   // the temporal-blocking prototype
     awe_status adjoint(const float* resid, float* src_adj, float* grad_phys, hipStream_t s);
     awe_status forward_begin(const float* wavelet, float* traces, int K, hipStream_t s);
     awe_status forward_advance(int max_steps, hipStream_t s, bool* done);

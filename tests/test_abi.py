@@ -114,3 +114,4 @@ def test_null_arguments_of_the_newer_calls():
     assert L.awe_sum_fields(C.c_void_p(16), parts, 1, 4, None) == _lib.AWE_EINVAL   # a NULL part
     assert L.awe_sum_fields(C.c_void_p(16), parts, 0, 4, None) == _lib.AWE_EINVAL   # no parts
     assert L.awe_sum_fields(C.c_void_p(16), parts, 65, 4, None) == _lib.AWE_EINVAL  # too many parts
+    assert L.awe_step2_blocked(None, 1, 0, None) == _lib.AWE_EINVAL
