@@ -574,8 +574,9 @@ struct TuneEntry {
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneEntry> g_tune_cache;
-// Smallest grids worth timing: a 3-D tuning pass costs ~100 stencil launches
-// of the plan's own size, a 2-D pass a few milliseconds at most.
+// Smallest grids worth timing: a 3-D tuning pass times each of its up to 78
+// candidates twice for about 1 ms (at least four launches), 0.2-0.4 s, a 2-D
+// pass a few tens of milliseconds.
 constexpr int64_t kTuneMinPoints3 = 4 << 20;
 constexpr int64_t kTuneMinPoints2 = 1 << 16;
 
@@ -683,21 +684,33 @@ awe_status Plan::tune(bool img, hipStream_t user_stream) {
                      : StepArgs{w0, w1, w1, coef, d_ez, d_ey, d_ex, nullptr, nullptr};
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
-    // two interleaved rounds of four timed launches (after one untimed); a
-    // candidate's time is its faster round
+    // two interleaved rounds of timed launches (after one untimed); a
+    // candidate's time is its faster round.  Each timing spans about 1 ms
+    // (at least four launches): with four launches of a ~50 us step, run-to-run
+    // noise let a 4% slower shape win now and then.
     std::vector<float> best_of(cand.size(), 1e30f);
-    for (int round = 0; round < 2 && e == hipSuccess; ++round) {
-        for (size_t i = 0; e == hipSuccess && i < cand.size(); ++i) {
+    auto time_cand = [&](size_t i, int reps) {
+        e = launch_step(L, k, a, img ? kStepImaging : kStepPlain, cand[i].cfg, cand[i].zchunk, s);
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        for (int w = 0; w < reps && e == hipSuccess; ++w)
             e = launch_step(L, k, a, img ? kStepImaging : kStepPlain, cand[i].cfg, cand[i].zchunk, s);
-            if (e == hipSuccess) e = hipEventRecord(e0, s);
-            for (int w = 0; w < 4 && e == hipSuccess; ++w) e = launch_step(L, k, a, img ? kStepImaging : kStepPlain, cand[i].cfg, cand[i].zchunk, s);
-            if (e == hipSuccess) e = hipEventRecord(e1, s);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0.f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e == hipSuccess) best_of[i] = std::min(best_of[i], ms);
-        }
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        return e == hipSuccess ? ms / reps : 1e30f;
+    };
+    int reps = 4;
+    if (e == hipSuccess && !cand.empty()) {
+        const float per = time_cand(0, 4);     // a first estimate of one launch
+        if (e == hipSuccess && per > 0.f && per < 1e29f)
+            reps = std::max(4, std::min(32, (int)std::ceil(1.0f / per)));
     }
+    for (int round = 0; round < 2 && e == hipSuccess; ++round)
+        for (size_t i = 0; e == hipSuccess && i < cand.size(); ++i) {
+            const float per = time_cand(i, reps);
+            if (e == hipSuccess) best_of[i] = std::min(best_of[i], per);
+        }
     // near-equal timings are a tie, settled by the longest z-chunk (tune_policy.hpp)
     const int pick = pick_timed_shape(cand.size(), best_of.data(), [&](size_t i) { return cand[i].zchunk; });
     const LaunchShape best = pick >= 0 ? cand[pick] : shape;
