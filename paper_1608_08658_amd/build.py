@@ -21,7 +21,7 @@ OUT = os.path.join(HERE, "libawe.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
 SOURCES = ["kernels_stencil_hi.hip", "kernels_stencil_lo.hip", "kernels_stencil.hip", "kernels_stencil2d_tb.hip",
-           "kernels_stencil3d_tb.hip",
+           "kernels_stencil3d_tb.hip", "kernels_born3d.hip",
            "kernels_aux.hip",
            "noalloc.hip", "engine.cpp", "checkpoint.cpp", "api.cpp", "server.cpp"]
 

@@ -138,6 +138,17 @@ int tb_tile();
 int tb_max_tile_receivers();
 // (uc, up) = (u[n0], u[n0-1]) -> (out_c, out_p) = (u[n0+nsteps], u[n0+nsteps-1]);
 // the outputs must be distinct from the inputs (tiles read halos of others).
+// One 3-D Born time step as a single sweep (kernels_born3d.hip): the
+// background u and the scattered du advance together, t = the background's
+// second time difference in a register; the source (at most kFuseMaxNodes
+// nodes) goes into u[n+1] and t, the receivers sample du[n].
+struct BornArgs {
+    const float *u, *up, *du, *dup, *coef, *dm, *eta_z, *eta_y, *eta_x;
+    float *out, *dout;           // u[n+1], du[n+1]; may alias up, dup (in-place update)
+};
+hipError_t launch_born3d(const Layout& L, const StencilCoef& k, const BornArgs& a, int zchunk, hipStream_t s,
+                         const FusedSparse& fs);
+
 // Two 3-D plain steps per z-sweep without point operators, half-widths
 // 1..kTb3MaxHalf, fields under 2 GB (kernels_stencil3d_tb.hip): o1 = u[n+1],
 // o2 = u[n+2] from uc = u[n], up = u[n-1]; the outputs alias neither input.

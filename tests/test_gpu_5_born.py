@@ -89,3 +89,28 @@ def test_born_fused_point_operators_bitwise(monkeypatch, kind):
         plan.close()
     assert np.any(outs[0] != 0.0)
     assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("order", [2, 8, 16])
+def test_born_one_sweep_bitwise_equal_to_two_launches(monkeypatch, order):
+    # 3-D: the background and the scattered step in one sweep (t in a
+    # register, the source injected into u and t inside the sweep) give the
+    # bits of the save-t and born launches; the source cell straddles a tile
+    # row seam (y 15/16) and a z-chunk seam, receivers sample du.
+    shot, dt, w, dm = _case("3d", order, 870 + order)
+    h = shot.spacing
+    shot.src_coords = np.array([[(27.5 - shot.nbl) * h[0], (15.5 - shot.nbl) * h[1], (63.5 - shot.nbl) * h[2]]])
+    monkeypatch.setenv("AWE_TILE", "1,28")
+    outs = []
+    for env in (None, "0"):
+        if env is None:
+            monkeypatch.delenv("AWE_BORN_FUSED", raising=False)
+        else:
+            monkeypatch.setenv("AWE_BORN_FUSED", env)
+        plan = gpu_plan(shot, dt)
+        plan.set_model(dev(shot.m))
+        outs.append(host(plan.born(dev(w), dev(dm))))
+        plan.close()
+    log(f"order {order}: max |J dm| {np.abs(outs[0]).max():.3e}")
+    assert np.any(outs[0] != 0.0)
+    assert np.array_equal(outs[0], outs[1])
