@@ -86,6 +86,16 @@ born3d(BornArgs a, StencilCoef k, Geo3 g, int zchunk, FusedSparse fs) {
         v_hyr[i] = v_ld + rowb(y);
         asm volatile("" : "+v"(v_hyr[i]));
     }
+    // whether a source node lies in this workgroup's tile and chunk (uniform):
+    // the per-plane injection below runs in those workgroups only, so the
+    // others never wait on the node table's scalar loads (a copy of the
+    // sweep without the injection for them took 40% more registers)
+    bool wg_inj = false;
+    for (int j = 0; j < fs.inj.nrows; ++j) {
+        const int zj = fs.inj_zyx[3 * j], yj = fs.inj_zyx[3 * j + 1], xj = fs.inj_zyx[3 * j + 2];
+        wg_inj = wg_inj || (zj >= z0 && zj < z1 && yj >= yb && yj < yb + TY && xj >= (int)bx * kTileX &&
+                            xj < (int)bx * kTileX + kTileX);
+    }
     const float exv = x < g.nx ? a.eta_x[x] : 0.f;
     float eyv[RY];
 #pragma unroll
@@ -186,7 +196,7 @@ born3d(BornArgs a, StencilCoef k, Geo3 g, int zchunk, FusedSparse fs) {
         }
         // the source into u[n+1] and t at its nodes in this plane (the
         // arithmetic of inj_apply, with C, the stored value and t in registers)
-        for (int j = 0; j < fs.inj.nrows; ++j) {
+        for (int j = 0; wg_inj && j < fs.inj.nrows; ++j) {
             if (fs.inj_zyx[3 * j] != z) continue;                 // uniform
             const int yj = fs.inj_zyx[3 * j + 1], xj = fs.inj_zyx[3 * j + 2];
             if (xj != x || yj < y0 || yj >= y0 + RY) continue;
