@@ -175,7 +175,11 @@ step3d_tb2(const float* uc, const float* up, float* o1, float* o2, const float* 
         // one barrier per plane orders the staging writes before the reads
         // of this plane, the ring write of plane zl - 1 before level 2 reads
         // it M planes later, and the last level-2 read of a ring slot before
-        // level 1 overwrites it (the slot of zl last held zl - M - 1)
+        // level 1 overwrites it (the slot of zl last held zl - M - 1).  Ring
+        // slots count from the chunk's first level-1 plane zs, which is
+        // negative in a chunk that starts less than M planes into the grid:
+        // a slot taken as zl % NS would then be negative and land in the
+        // staging planes that other waves are reading.
         lds_barrier();
 
         // level 1: u[n+1](zl) on the whole region, 0 outside the grid
@@ -200,7 +204,7 @@ step3d_tb2(const float* uc, const float* up, float* o1, float* o2, const float* 
             const float v = (zin && xin && yin[r]) ? (u0 - d) + t : 0.f;
             Q2(r, NQ - 1) = v;
             CQ(r, M) = c[r];
-            ring[zl % NS][ty * RY + r][tx] = v;
+            ring[(zl - zs) % NS][ty * RY + r][tx] = v;
             if (zl >= z0 && zl < z1) bstore<AWE_CPOL_STREAM>(r_o1, v, v_st[r], soff(zl));
         }
         // level 2: u[n+2](zl - M), once level 1 is M planes ahead
@@ -209,7 +213,7 @@ step3d_tb2(const float* uc, const float* up, float* o1, float* o2, const float* 
             const float ezx2 = eta_z[z2] + exv;
 #pragma unroll
             for (int r = 0; r < RY; ++r) {
-                const float* ly = &ring[z2 % NS][ty * RY + r][tx];
+                const float* ly = &ring[(z2 - zs) % NS][ty * RY + r][tx];
                 float lap = k.c0 * Q2(r, M);
 #pragma unroll
                 for (int kk = 1; kk <= M; ++kk) {

@@ -55,6 +55,33 @@ def test_two_steps_per_sweep_equal_two_single_steps(order, shape, npairs, zchunk
         assert np.array_equal(a, b), name
 
 
+# chunks starting fewer than M planes into the grid compute level-1 planes at
+# z < 0, whose LDS ring slots once aliased the staging planes other waves were
+# reading (results then varied from run to run near tile seams); each case
+# runs the blocked launch three times from one state
+@pytest.mark.parametrize("order,zchunk", [(8, 3), (6, 2), (6, 16), (4, 1), (2, 5)])
+def test_two_steps_per_sweep_repeatable_near_the_first_plane(order, zchunk):
+    shot = small_3d_shot(1200 + order, order, shape=(24, 60, 125), nbl=4)
+    log(f"case order {order} zchunk {zchunk}")
+    dt = shot_dt(shot)
+    rng = np.random.default_rng(11)
+    P = tuple(n + 2 * shot.nbl for n in shot.shape)
+    u0 = synth.random_state(rng, P, 3.0).astype(np.float32)
+    um = (u0 * 0.999).astype(np.float32)
+    plan = gpu_plan(shot, dt, nt=5, src=np.zeros((0, 3)))
+    plan.set_model(dev(shot.m))
+    plan.set_state(dev(u0), dev(um))
+    plan.step(0, 4)
+    ref = [host(a) for a in plan.get_state()]
+    for rep in range(3):
+        plan.set_state(dev(u0), dev(um))
+        plan.step2_blocked(2, zchunk)
+        got = [host(a) for a in plan.get_state()]
+        for a, b, name in zip(got, ref, ("u", "u_prev")):
+            assert np.array_equal(a, b), f"{name}, run {rep}: {int((a != b).sum())} points differ"
+    plan.close()
+
+
 def test_two_steps_per_sweep_full_size():
     # the 336^3 forward workload's grid (256^3 + 40-point layer), order 8
     shot = synth.config_3d_forward(nt=5)
