@@ -1102,8 +1102,13 @@ awe_status Plan::born(const float* wavelet, const float* dm_phys, float* traces,
     prev = w1;
     float* dcur = b_du0;     // du[n]
     float* dprev = b_du1;    // du[n-1], overwritten in place by du[n+1]
+    // 3-D Born launches take their own z-chunk (8 planes below 27M points,
+    // as the built-in shape, else 56): the forward's tuned chunk can be long
+    // (112 planes at 336^3 order 8), which leaves the one-sweep kernel, with
+    // its larger register footprint, too few workgroups (396 against 301 ms
+    // in 56-plane chunks)
     const int cfg = g.ndim == 3 ? 3 : 0;
-    const int zc = fwd_shape.zchunk;
+    const int zc = g.ndim == 3 ? balanced_zchunk(L.n[0], L.points() < 27000000 ? 8 : 56) : fwd_shape.zchunk;
     // 3-D steps in one sweep for both fields (1.2-1.3x over the two launches
     // of the save-t and born modes at 336^3 order 8, bit-identical);
     // AWE_BORN_FUSED=0 keeps the two launches (for A/B tests)

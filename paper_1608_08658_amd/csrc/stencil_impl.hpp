@@ -36,9 +36,12 @@
 //     arithmetic of the planes in between;
 //   * each thread owns RY consecutive y rows, so y-neighbours inside its own
 //     rows come from registers;
-//   * a wavefront owns 64 columns of one thread row, so row indices and row
-//     offsets are wave-uniform (scalar registers): the vector registers hold
-//     the queue, the prefetched values and one column offset per lane.
+//   * a wavefront owns 64 columns of one thread row; each lane keeps one
+//     column-plus-row offset per row in a vector register, set once, and a
+//     load's scalar offset carries the z plane alone;
+//   * steps that load one plane ahead run the z loop in whole rounds of the
+//     queue's period without a per-plane guard, so the loads of a plane stay
+//     in flight across the plane computed meanwhile.
 // A step may also carry its time step's point operators (FusedSparse):
 // workgroups appended to the tile grid sample the input, and in plain and
 // save-t steps the workgroup whose tile holds a source node adds the
@@ -340,7 +343,7 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk, FusedSparse fs) {
     // advancing by one per plane, and plane z0 + i uses prefetch set i % PF.
     // The loop is unrolled NQ2 times so PH and the set are compile-time
     // constants and no register moves are needed.
-    auto one_plane = [&](auto ph, auto set, int z) {
+    auto one_plane = [&](auto ph, auto set, auto whole, int z) {
         constexpr int PH = decltype(ph)::value;
         Pre& P = pre[decltype(set)::value];
         auto Q = [&](int r, int j) -> float& { return q[r][(j + PH) % NQ2]; };
@@ -370,13 +373,14 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk, FusedSparse fs) {
             if (MODE == kStepImaging || MODE == kStepBorn) { s[r] = P.sv[r]; gg[r] = P.gv[r]; }
         }
         const float ezv = P.ezn;
-        // the set is consumed: refill it with plane z + PF.  The order-16
-        // plain step refills without a branch (past the chunk's end it loads
-        // the last plane again, unused), since the join of the branch costs
-        // register moves of the whole set: 404 -> 381 us per 480^3 step in
-        // the best launch shape.  At orders 10-14 and with imaging the
-        // branch-free form was measured slower.
-        if constexpr (M == 8 && MODE == kStepPlain) fetch(P, min(z + PF, z1 - 1));
+        // the set is consumed: refill it with plane z + PF.  Inside a whole
+        // round the refill takes no branch (past the chunk's end it loads
+        // the last plane again, unused): a branch's join would merge the
+        // refilled set with the old one, and the register copies that merge
+        // needs wait for the loads just issued.  The order-16 plain step
+        // refills without a branch in guarded planes too (404 -> 381 us per
+        // 480^3 step; at orders 10-14 and with imaging that was slower).
+        if constexpr (decltype(whole)::value || (M == 8 && MODE == kStepPlain)) fetch(P, min(z + PF, z1 - 1));
         else if (z + PF < z1) fetch(P, z + PF);
         lds_barrier();
 
@@ -423,13 +427,34 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk, FusedSparse fs) {
         }
     };
     // before plane z0 the queue holds planes z0-M .. z0+M-1 in physical slots
-    // 1..NQ-1, i.e. logical slot j sits in (j + 1) % NQ2: the first plane has PH = 1
+    // 1..NQ-1, i.e. logical slot j sits in (j + 1) % NQ2: the first plane has PH = 1.
+    // Steps that load one plane ahead run whole rounds of NQ2 planes
+    // unguarded and test each plane only in the chunk's last partial round.
+    // A guarded plane ends in a join where the refilled prefetch set meets
+    // the old one, and the register copies of that merge wait for the loads
+    // just issued, so no load outlived its plane (at order 8 every plane
+    // drained the memory counter): 110 -> 107 us per 336^3 order-8 step,
+    // 572 -> 553 us per 480^3 order-16 imaging step.  Plain steps of orders
+    // 10-16, which load two planes ahead, keep the guard on every plane: with
+    // whole rounds the 480^3 order-16 step took 387 against 376 us.
+    constexpr bool kWholeRounds = PF == 1;
     int z = z0;
+    if constexpr (kWholeRounds) {
+        while (z + NQ2 <= z1) {
+            static_for<NQ2>([&](auto s_) {
+                constexpr int PH = (decltype(s_)::value + 1) % NQ2;
+                one_plane(std::integral_constant<int, PH>{}, std::integral_constant<int, decltype(s_)::value % PF>{},
+                          std::true_type{}, z);
+                ++z;
+            });
+        }
+    }
     for (;;) {
         static_for<NQ2>([&](auto s_) {
             constexpr int PH = (decltype(s_)::value + 1) % NQ2;
             if (z < z1)
-                one_plane(std::integral_constant<int, PH>{}, std::integral_constant<int, decltype(s_)::value % PF>{}, z);
+                one_plane(std::integral_constant<int, PH>{}, std::integral_constant<int, decltype(s_)::value % PF>{},
+                          std::false_type{}, z);
             ++z;
         });
         if (z >= z1) break;
