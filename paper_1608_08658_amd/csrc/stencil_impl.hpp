@@ -437,6 +437,8 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk, FusedSparse fs) {
     // 572 -> 553 us per 480^3 order-16 imaging step.  Plain steps of orders
     // 10-16, which load two planes ahead, keep the guard on every plane: with
     // whole rounds the 480^3 order-16 step took 387 against 376 us.
+    // The partial round is straight-line code after the loop, not a second
+    // loop: as a loop it raised the order-8 kernels' registers by a third.
     constexpr bool kWholeRounds = PF == 1;
     int z = z0;
     if constexpr (kWholeRounds) {
@@ -448,8 +450,6 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk, FusedSparse fs) {
                 ++z;
             });
         }
-    }
-    for (;;) {
         static_for<NQ2>([&](auto s_) {
             constexpr int PH = (decltype(s_)::value + 1) % NQ2;
             if (z < z1)
@@ -457,7 +457,17 @@ step3d(StepArgs a, StencilCoef k, Geo3 g, int zchunk, FusedSparse fs) {
                           std::false_type{}, z);
             ++z;
         });
-        if (z >= z1) break;
+    } else {
+        for (;;) {
+            static_for<NQ2>([&](auto s_) {
+                constexpr int PH = (decltype(s_)::value + 1) % NQ2;
+                if (z < z1)
+                    one_plane(std::integral_constant<int, PH>{}, std::integral_constant<int, decltype(s_)::value % PF>{},
+                              std::false_type{}, z);
+                ++z;
+            });
+            if (z >= z1) break;
+        }
     }
 
     // Fused injection: the workgroup whose tile holds a node adds its
