@@ -258,7 +258,10 @@ def test_gradient_across_launch_shapes(monkeypatch, order):
     # the operator tolerance.  The grid is wider than two 128-point tiles (with
     # a ragged tail), so the two-wavefront tiles (4: 128 x 8, 5: 128 x 16) meet
     # x seams between their wavefronts and between tiles, and the chunks below
-    # the z extent meet z seams.
+    # the z extent meet z seams.  Steps that load one plane ahead run whole
+    # rounds of 2M+1 planes unguarded and the rest of a chunk guarded: chunks
+    # of 9 (order 8) and 17 or 34 planes (the order-16 imaging step) are whole
+    # rounds only, the others end in a partial round.
     shot = small_3d_shot(610 + order, order, shape=(40, 46, 150), nt=40)
     K = 8
     dt, w, d_obs = _gradient_case(shot, K)
@@ -267,7 +270,7 @@ def test_gradient_across_launch_shapes(monkeypatch, order):
     resid = (fwd["traces"] - d_obs).astype(np.float32)
     g_ref = oracle.fold_padding(op.adjoint(resid, history=fwd["history"])["grad_pad"], shot.nbl)
     outs = []
-    for cfg in ("0,9", "1,31", "3,56", "4,13", "4,28", "5,21", "5,84"):
+    for cfg in ("0,9", "1,31", "3,56", "4,13", "4,28", "5,21", "5,84", "2,17", "1,34"):
         monkeypatch.setenv("AWE_TILE", cfg)
         plan = gpu_plan(shot, dt)
         plan.set_model(dev(shot.m))
