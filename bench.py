@@ -41,25 +41,28 @@ def log(msg):
 PROFILE = os.path.join(ROOT, "profiles", "step3d_o8_336cube_forward.md")
 PROFILE_O16_STEP = os.path.join(ROOT, "profiles", "step3d_o16_480cube_forward.md")
 PROFILE_O16_IMAGING = os.path.join(ROOT, "profiles", "step3d_o16_480cube_gradient_imaging.md")
+PROFILE_BORN = os.path.join(ROOT, "profiles", "born3d_o8_336cube_born.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_1608_08658_amd", "csrc", "stencil_impl.hpp")
+BORN_SRC = (os.path.join(ROOT, "paper_1608_08658_amd", "csrc", "kernels_born3d.hip"), KERNEL_SRC)
 
 
 def kernel_source_digest(path=KERNEL_SRC):
-    """sha256 of the stencil source without its comments and blank lines:
-    recorded counters stay valid across edits of the comments, not of the
-    code."""
+    """sha256 of the kernel source (one path, or several read in order)
+    without its comments and blank lines: recorded counters stay valid across
+    edits of the comments, not of the code."""
     import hashlib
     import re
-    text = re.sub(r"/\*.*?\*/", "", open(path).read(), flags=re.S)
+    paths = (path,) if isinstance(path, str) else tuple(path)
+    text = re.sub(r"/\*.*?\*/", "", "\n".join(open(p).read() for p in paths), flags=re.S)
     lines = [re.sub(r"//.*$", "", line).rstrip() for line in text.splitlines()]
     return hashlib.sha256("\n".join(line for line in lines if line.strip()).encode()).hexdigest()
 
 
-def profiled_traffic(shape, path=PROFILE):
-    """HBM bytes per stencil launch from a committed rocprofv3 counter
-    summary (one entry per launch shape that was profiled), or None when the
-    kernel code has changed since the counters were taken or this launch
-    shape was not profiled."""
+def profiled_traffic(shape, path=PROFILE, src=KERNEL_SRC):
+    """HBM bytes per launch from a committed rocprofv3 counter summary (one
+    entry per launch shape that was profiled), or None when the kernel code
+    (``src``) has changed since the counters were taken or this launch shape
+    was not profiled."""
     try:
         digest, per_shape = None, {}
         for line in open(path):
@@ -71,7 +74,7 @@ def profiled_traffic(shape, path=PROFILE):
             elif t.startswith("shape ") and "traffic_bytes_per_launch" in t:
                 f = t.split()
                 per_shape[f[1].rstrip(":")] = float(f[f.index("traffic_bytes_per_launch") + 1])
-        if digest != kernel_source_digest():
+        if digest != kernel_source_digest(src):
             return None
         return per_shape.get(f"{shape[0]},{shape[1]}")
     except (OSError, ValueError, IndexError):
@@ -381,10 +384,15 @@ def bench_born(torch, awe, synth, n=256, nt=1000):
     gbs = 32.0 * npad * (shot.nt - 1) / t / 1e9
     log(f"Born modelling: {t * 1e3:.1f} ms, {npad * (shot.nt - 1) / t / 1e9:.1f} G updates/s of the pair, "
         f"{gbs:.0f} GB/s algorithmic ({100 * gbs / HBM_PEAK_GBS:.1f}%)")
+    # HBM bytes per launch from the committed counters of the one-sweep kernel
+    # on this grid (None if its code changed since or the grid differs)
+    traffic = profiled_traffic(("born", shot.shape[0] + 2 * shot.nbl), PROFILE_BORN, BORN_SRC)
     return {"workload": f"J dm on the {n}^3 order-8 forward workload ({'x'.join(map(str, shot.shape))} physical, "
                         f"{shot.nt} samples, {len(shot.rec_coords)} receivers), smooth 5% dm",
             "born_s": t, "pair_updates_per_s": npad * (shot.nt - 1) / t, "bytes_per_update": 32.0,
-            "algorithmic_GBps": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS, "finite": finite}
+            "algorithmic_GBps": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS, "finite": finite,
+            "kernel": "born3d<M=4> (both fields in one sweep per step)", "traffic": traffic,
+            "algorithmic_bytes_per_launch": 32.0 * npad}
 
 
 def bench_small_2d(torch, awe, synth, reps=5):
